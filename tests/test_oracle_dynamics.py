@@ -1,0 +1,262 @@
+"""Pins of the oracle's time stepping: exact properties of the scheme and
+closed-form physics the model must reproduce (Sec. III, Sec. IV)."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1109_6672_amd import workloads as W
+
+
+def _run(p, fields=None, steps=0):
+    o = O.Oracle(p)
+    o.init(*(fields if fields is not None else W.rest_fields(p)))
+    o.step(steps)
+    return o
+
+
+# ---------------------------------------------------------------- exact properties
+def test_streaming_moves_a_delta_by_e_alpha():
+    """Eq. 45 with periodic wrap: population alpha moves by e_alpha per step."""
+    ex, ey, _ = O.lattice()
+    p = W.periodic(7, 5)
+    o = O.Oracle(p).init()
+    pops = np.zeros((18, 5, 7))
+    for k in range(18):
+        pops[k, 2, 3] = k + 1.0
+    o.set_pops(pops)
+    o.stream_only(3)
+    got = o.pops()
+    for k in range(18):
+        a = k % 9
+        want = np.zeros((5, 7))
+        want[(2 + 3 * ey[a]) % 5, (3 + 3 * ex[a]) % 7] = k + 1.0
+        np.testing.assert_array_equal(got[k], want)
+
+
+@pytest.mark.parametrize("collision", ["mrt", "bgk"])
+def test_uniform_state_is_a_fixed_point(collision):
+    p = W.periodic(6, 5)
+    p["collision"] = collision
+    f = tuple(np.full((5, 6), v) for v in (1.1, 0.03, -0.02, 1.3))
+    o = _run(p, f, 20)
+    for a, want in zip(o.macros(), (1.1, 0.03, -0.02, 1.3)):
+        np.testing.assert_allclose(a, want, rtol=0, atol=1e-13)
+
+
+@pytest.mark.parametrize("energy", ["total", "internal"])
+def test_periodic_conservation(energy):
+    """Periodic, no force: mass, momentum and sum h are invariants of the step."""
+    p = W.periodic(16, 12)
+    p.update(energy=energy, heating=(energy == "total"))
+    o = _run(p, W.gaussian_fields(p, sigma=2e-2))
+    d0 = o.diag()
+    o.step(1000)
+    d1 = o.diag()
+    assert d1["bad"] == 0
+    assert abs(d1["mass"] - d0["mass"]) < 1e-12 * d0["mass"]
+    assert abs(d1["energy"] - d0["energy"]) < 1e-12 * d0["energy"]
+    assert abs(d1["jx"] - d0["jx"]) < 1e-12 and abs(d1["jy"] - d0["jy"]) < 1e-12
+
+
+def test_gravity_adds_momentum_at_a_fixed_rate():
+    p = W.periodic(8, 8)
+    p["g"] = 1e-4
+    o = _run(p, W.gaussian_fields(p))
+    d0 = o.diag()
+    o.step(10)
+    d1 = o.diag()
+    # after the first step every node gains a_y = -rho g per step (total: -g * mass)
+    assert abs((d1["jy"] - d0["jy"]) - (-1e-4 * d0["mass"] * 10)) < 1e-12
+    assert abs(d1["mass"] - d0["mass"]) < 1e-12
+
+
+def _mirror_x(fields):
+    rho, ux, uy, T = fields
+    return rho[:, ::-1], -ux[:, ::-1], uy[:, ::-1], T[:, ::-1]
+
+
+def _transpose(fields):
+    rho, ux, uy, T = fields
+    return rho.T, uy.T, ux.T, T.T
+
+
+@pytest.mark.parametrize("collision", ["mrt", "bgk"])
+def test_mirror_and_transpose_symmetry(collision):
+    """A reflected or transposed initial field evolves into the reflected or
+    transposed solution: catches any sign/index asymmetry between directions."""
+    p = W.periodic(12, 12)
+    p.update(collision=collision, s_e=1.1, s_zeta=1.3, s_q=1.4)
+    f = W.gaussian_fields(p, sigma=2e-2)
+    ref = _run(p, f, 30).macros()
+    m = _run(p, _mirror_x(f), 30).macros()
+    for a, b in zip(_mirror_x(ref), m):
+        np.testing.assert_allclose(b, a, atol=1e-14)
+    t = _run(p, _transpose(f), 30).macros()
+    for a, b in zip(_transpose(ref), t):
+        np.testing.assert_allclose(b, a, atol=1e-14)
+
+
+def test_correction_term_changes_the_solution_only_through_theta():
+    """With T = T0 everywhere Q vanishes and the correction term has no effect."""
+    p = W.periodic(10, 10)
+    rho, ux, uy, _ = W.gaussian_fields(p, sigma=1e-2)
+    T = np.ones_like(rho)
+    a = _run(dict(p, correction=True, heating=False), (rho, ux, uy, T), 1).pops()
+    b = _run(dict(p, correction=False, heating=False), (rho, ux, uy, T), 1).pops()
+    np.testing.assert_allclose(a, b, atol=1e-16)
+    f = W.gaussian_fields(p, sigma=1e-2)
+    a = _run(dict(p, correction=True), f, 5).pops()
+    b = _run(dict(p, correction=False), f, 5).pops()
+    assert np.abs(a - b).max() > 1e-9
+
+
+# ---------------------------------------------------------------- closed-form physics
+def test_couette_analytic_profiles():
+    """Couette flow between walls at T0: u = U eta and
+    T - T0 = Pr U^2 / (2 c_p) eta (1 - eta) (viscous heating, Eq. 29c)."""
+    p = W.couette()
+    o = _run(p, steps=20000)
+    rho, ux, uy, T = o.macros()
+    ny = p["ny"]
+    eta = np.arange(ny) / (ny - 1)
+    U = 0.1
+    cp = (p["b"] + 2) * p["R"] / 2
+    Tw = 1 + p["Pr"] * U * U / (2 * cp) * eta * (1 - eta)
+    assert np.abs(ux[:, 1] - U * eta).max() < 1e-4 * U
+    assert np.abs(uy).max() < 1e-6
+    rise = Tw.max() - 1
+    assert np.abs(T[:, 1] - Tw).max() < 2e-3 * rise
+    # walls report their prescribed values exactly
+    assert ux[0, 0] == 0.0 and ux[-1, 0] == U and T[0, 0] == 1.0 and T[-1, 0] == 1.0
+
+
+def _standing_wave(p, nx, steps, eps=1e-4):
+    """Adiabatic standing sound wave; returns the rho mode amplitude history."""
+    gamma = (p["b"] + 2) / p["b"]
+    x = np.arange(nx)
+    k = 2 * math.pi / nx
+    c = np.cos(k * x)[None, :]
+    ny = p["ny"]
+    rho = np.ones((ny, nx)) + eps * c
+    T = np.ones((ny, nx)) + (gamma - 1) * eps * c if p["coupled"] else np.ones((ny, nx))
+    o = O.Oracle(p).init(rho, np.zeros((ny, nx)), np.zeros((ny, nx)), T)
+    amp = []
+    for _ in range(steps):
+        r = o.macros()[0]
+        amp.append(((r - 1) * c).mean() * 2)
+        o.step(1)
+    return k, np.array(amp)
+
+
+def _fit_damped_cosine(a):
+    """Frequency from zero crossings, damping from the decay of the extrema."""
+    s = np.sign(a)
+    idx = np.where(s[1:] != s[:-1])[0]
+    t0 = [i + a[i] / (a[i] - a[i + 1]) for i in idx]
+    half_periods = np.diff(t0)
+    omega = math.pi / half_periods.mean()
+    peaks = [(j, abs(a[j])) for j in range(1, len(a) - 1) if abs(a[j]) >= abs(a[j - 1]) and abs(a[j]) >= abs(a[j + 1])]
+    tt = np.array([q[0] for q in peaks], float)
+    yy = np.log([q[1] for q in peaks])
+    gam = -np.polyfit(tt, yy, 1)[0]
+    return omega, gam
+
+
+@pytest.mark.parametrize("b", [3.0, 5.0])
+def test_sound_speed_and_damping_coupled(b):
+    """Coupled model: omega = k sqrt(gamma R T0); damping
+    Gamma = k^2/2 [(4/3) nu + nu_B + (gamma-1) chi], nu_B = 2(1/3 - 1/b) nu (Eq. 29-30, 56)."""
+    nx = 128
+    p = W.periodic(nx, 1, tau_f=0.8)
+    p.update(b=b, correction=True, heating=True, s_q=1.5)
+    k, a = _standing_wave(p, nx, 2000)
+    omega, gam = _fit_damped_cosine(a)
+    gamma = (b + 2) / b
+    assert abs(omega / (k * math.sqrt(gamma / 3)) - 1) < 2e-4
+    nu = (0.8 - 0.5) / 3
+    chi = nu / p["Pr"]
+    want = 0.5 * k * k * ((4 / 3) * nu + 2 * (1 / 3 - 1 / b) * nu + (gamma - 1) * chi)
+    assert abs(gam / want - 1) < 0.01
+
+
+def test_sound_speed_decoupled():
+    """Decoupled model (theta = 1): isothermal sound speed sqrt(R T0)."""
+    nx = 128
+    p = W.periodic(nx, 1, tau_f=0.8)
+    p.update(coupled=False)
+    k, a = _standing_wave(p, nx, 2000)
+    omega, _ = _fit_damped_cosine(a)
+    assert abs(omega / (k * math.sqrt(1 / 3)) - 1) < 2e-4
+
+
+# ---------------------------------------------------------------- acoustic channel (Sec. IV-B)
+def _acoustic_envelope(Pr, b, coupled, nx=600, t_m=800, lam=50.0, mu=0.1):
+    gamma = (b + 2) / b
+    cs = math.sqrt(gamma / 3)
+    P = lam / cs
+    U = cs * 0.01  # U = c_s delta_rho / rho0 with delta_rho = 0.01 rho0 (Eq. 54)
+    p = W.channel(nx=nx, ny=2, U0=U, period=P, tau_f=3 * mu + 0.5, Pr=Pr, b=b, correction=False,
+                  coupled=coupled)
+    o = O.Oracle(p).init(*W.rest_fields(p))
+    o.step(t_m - int(P) - 1)
+    env = np.zeros(nx)
+    for _ in range(int(P) + 1):
+        o.step(1)
+        env = np.maximum(env, np.abs(o.macros()[1][0]))
+    fp = cs / lam
+    cv, cp = b / 2 / 3, (b + 2) / 2 / 3
+    beta = 2 * math.pi ** 2 * fp ** 2 / cs ** 3 * ((4 / 3) * mu + 2 * (1 / 3 - 1 / b) * mu + (1 / cv - 1 / cp) * mu * cp / Pr)
+    x = np.arange(nx)
+    xmax = min(500, int(cs * (t_m - P)) - 20)
+    sel = (x >= 20) & (x <= xmax)
+    return x[sel], env[sel], U * np.exp(-beta * x[sel]), beta
+
+
+@pytest.mark.parametrize("Pr,b", [(0.71, 3.0), (5.0, 3.0), (2.0, 5.0)])
+def test_acoustic_attenuation_eq56(Pr, b):
+    """Velocity amplitude U(x) = U exp(-beta x) with beta of Eq. 56."""
+    x, env, want, beta = _acoustic_envelope(Pr, b, True)
+    fit = -np.polyfit(x, np.log(env), 1)[0]
+    assert abs(fit / beta - 1) < 0.03
+    assert np.abs(env / want - 1).max() < 0.04
+
+
+def test_decoupled_model_misses_the_attenuation():
+    """With theta = 1 the wave travels at sqrt(R T0) and the amplitude profile
+    departs from Eq. 55 (Fig. 5 and the discussion after it)."""
+    x, env, want, beta = _acoustic_envelope(2.0, 3.0, False)
+    assert np.abs(env / want - 1).max() > 0.3
+
+
+def test_inlet_and_outlet_report_their_boundary_values():
+    p = W.channel(nx=40, ny=3, U0=0.01, period=20.0)
+    o = O.Oracle(p).init(*W.rest_fields(p))
+    o.step(37)
+    rho, ux, uy, T = o.macros()
+    gamma = 5.0 / 3.0
+    cs = math.sqrt(gamma / 3)
+    s = math.sin(2 * math.pi * 37 / 20.0)
+    np.testing.assert_allclose(ux[:, 0], 0.01 * s, rtol=0, atol=1e-17)
+    np.testing.assert_allclose(rho[:, 0], 1 + 0.01 * s / cs, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(T[:, 0], 1 + (gamma - 1) * 0.01 * s / cs, rtol=0, atol=1e-15)
+    for a in (rho, ux, uy, T):
+        np.testing.assert_array_equal(a[:, -1], a[:, -2])
+    pops = o.pops()
+    np.testing.assert_array_equal(pops[:, :, -1], pops[:, :, -2])
+
+
+def test_cavity_walls_and_corners():
+    """Dirichlet walls report T_w and u = 0; adiabatic walls have zero normal
+    gradient to second order; corners take the vertical wall's temperature."""
+    p = W.cavity(16, 1e4, 0.2, 0.05)
+    o = O.Oracle(p).init(*W.noisy_temperature_fields(p))
+    o.step(300)
+    rho, ux, uy, T = o.macros()
+    assert np.all(T[:, 0] == 1.1) and np.all(T[:, -1] == 0.9)
+    assert np.all(ux[0] == 0) and np.all(uy[-1] == 0) and np.all(ux[:, 0] == 0)
+    np.testing.assert_allclose(T[0, 1:-1], (4 * T[1, 1:-1] - T[2, 1:-1]) / 3, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(T[-1, 1:-1], (4 * T[-2, 1:-1] - T[-3, 1:-1]) / 3, rtol=0, atol=1e-15)
+    # pressure extrapolation: rho_b T_b = rho_f T_f at Dirichlet walls
+    np.testing.assert_allclose(rho[1:-1, 0] * T[1:-1, 0], rho[1:-1, 1] * T[1:-1, 1], rtol=1e-15)

@@ -1,0 +1,38 @@
+"""The oracle against the numbers the paper prints (Table I)."""
+import json
+import os
+
+import pytest
+
+from oracle import oracle as O
+from paper_1109_6672_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _table1():
+    with open(os.path.join(GOLD, "table1_couette.json")) as fh:
+        return json.load(fh)["rows"]
+
+
+def test_table1_analytic_column_is_eq52a():
+    """The analytic column of Table I is Eq. 52a at the lower wall (u_x = 0)."""
+    for Pr, Ma, _, Ta, _ in _table1():
+        gamma = 5.0 / 3.0
+        assert abs(1 + Pr * (gamma - 1) / 2 * Ma * Ma - Ta) < 6e-5
+
+
+@pytest.mark.parametrize("row", [0])
+def test_table1_couette_lower_wall_temperature(row):
+    """Adiabatic lower wall, mu ~ T, 10 x 60 fluid nodes between the walls:
+    the relative error E_r of the wall temperature rise is within the 1 % the
+    paper reports (Sec. IV-A)."""
+    Pr, Ma, T_paper, Ta, Er_paper = _table1()[row]
+    p = W.couette_paper(Pr, Ma, nx=10, ny=62)
+    o = O.Oracle(p).init(*W.rest_fields(p))
+    o.step(50000)
+    T = o.macros()[3]
+    Ta_exact = 1 + Pr * (2.0 / 3.0) / 2 * Ma * Ma
+    Er = abs((T[0, 0] - 1) - (Ta_exact - 1)) / (Ta_exact - 1)
+    assert Er < 0.01
+    assert abs(T[0, 0] - T_paper) < 0.01 * (T_paper - 1)
