@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Throughput of the fused collide-and-stream step on one MI355X.
+
+Workload (the bandwidth sweep of the coupled DDF model): a fully periodic
+8192 x 8192 D2Q9 grid, total-energy form with viscous heating and the
+correction term, tau_f = 0.8, Pr = 0.71, b = 3, seeded Gaussian perturbations
+(sigma = 1e-3) of rho, u and T.  One step = one fused launch over every node
+(gather 18 populations, moments, correction term, MRT f, BGK h with coupling,
+store 18 populations).  value = MLUPS (million node updates per second) with
+FP32 population storage; the 16-bit storage run and the smaller grids are
+reported beside it.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_NODE = {"f32": 144, "f16": 72, "bf16": 72}  # 18 loads + 18 stores per node-update
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_1109_6672_amd", "csrc", "lbddf.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(key: str, nodes: int):
+    """HBM bytes per launch from the committed rocprofv3 PMC summary, if it was
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    e = t.get(key)
+    if not e or e.get("kernel_source_sha") != kernel_source_hash():
+        return None
+    return e.get("bytes_per_launch")
+
+
+def time_gpu(n: int, storage: str, steps: int, warmup: int, strip_rows: int = 0):
+    import torch
+
+    from paper_1109_6672_amd import lbddf, workloads as W
+
+    p = W.periodic(n, storage=storage)
+    fields = W.gaussian_fields(p, sigma=1e-3)
+    s = lbddf.Solver(p, device=0)
+    s.init(*fields)
+    del fields
+    if strip_rows:
+        s.set_strip_rows(strip_rows)
+    s.step(warmup)
+    stream = s.stream
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    s.step(steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = start.elapsed_time(stop)
+    d = s.diag(check=False)
+    nodes = n * n
+    out = dict(n=n, storage=storage, steps=steps, ms_total=ms, ms_per_step=ms / steps, wall_s=wall,
+               mlups=nodes * steps / (ms * 1e-3) / 1e6, strip_rows=s.strip_rows, bad_nodes=d["bad"])
+    out["gbs"] = BYTES_PER_NODE[storage] * nodes / (out["ms_per_step"] * 1e-3) / 1e9
+    s.close()
+    del s
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(seconds: float):
+    """The FP64 oracle as it stands on the host cores, on a bounded sample of
+    the same workload (periodic 512 x 512, same recipe), until `seconds` pass."""
+    from oracle import oracle as O
+    from paper_1109_6672_amd import workloads as W
+
+    n = 512
+    p = W.periodic(n)
+    o = O.Oracle(p).init(*W.gaussian_fields(p, sigma=1e-3))
+    o.step(1)
+    steps = 0
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        o.step(2)
+        steps += 2
+    t = time.perf_counter() - t0
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=n * n * steps / t / 1e6, unit="MLUPS", cores=cores, kind="oracle",
+                sample=f"periodic {n}x{n}, same recipe, {steps} steps in {t:.1f} s (FP64, OpenMP over rows)")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=8192, help="grid edge of the headline workload")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit and smaller-grid runs")
+    ap.add_argument("--only", default="", help="storage of a single run (profiling): f32 | f16 | bf16")
+    ap.add_argument("--copy-only", action="store_true",
+                    help="HBM counter calibration: 5 plain device copies of 2 GiB (torch copy kernel)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU halo-exchange design is described, not built).", file=sys.stderr)
+        sys.exit(2)
+
+    if args.copy_only:
+        import torch
+
+        x = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
+        x.fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 5
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": x.numel() * 4,
+                          "copy_GBs": 2 * x.numel() * 4 / dt / 1e9}), flush=True)
+        return
+
+    if args.only:
+        r = time_gpu(args.n, args.only, args.steps, args.warmup)
+        print(json.dumps(r), flush=True)
+        return
+
+    head = time_gpu(args.n, "f32", args.steps, args.warmup)
+    print(f"# f32 {args.n}^2: {head['mlups']:.0f} MLUPS, {head['gbs']:.0f} GB/s algorithmic", file=sys.stderr,
+          flush=True)
+    extra = {}
+    if not args.no_extra:
+        for storage, n in (("f16", args.n), ("bf16", args.n), ("f32", 4096), ("f16", 4096), ("f32", 1024)):
+            if n > args.n:
+                continue
+            r = time_gpu(n, storage, args.steps, args.warmup)
+            extra[f"{storage}_{n}"] = {k: r[k] for k in ("mlups", "gbs", "ms_per_step", "strip_rows")}
+            print(f"# {storage} {n}^2: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+    nodes = args.n * args.n
+    alg = BYTES_PER_NODE["f32"] * nodes
+    achieved = alg / (head["ms_per_step"] * 1e-3) / 1e9
+    traffic = measured_traffic(f"lb_step_periodic{args.n}_f32", nodes)
+    line = {
+        "metric": "MLUPS (FP32 storage) + % HBM roofline",
+        "value": round(head["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(head["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"coupled DDF D2Q9, periodic {args.n}x{args.n}, Gaussian sigma=1e-3 on rho,u,T, "
+                               "total energy + heating + correction, MRT, FP32 storage",
+                   "nodes": nodes, "strip_rows": head["strip_rows"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
+                     "bytes_per_node": BYTES_PER_NODE["f32"], "kernel": "k_step<F32, periodic>"},
+        "extra": extra,
+        "bad_nodes": head["bad_nodes"],
+    }
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

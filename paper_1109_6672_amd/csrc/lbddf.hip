@@ -1,0 +1,1208 @@
+// lbddf.hip - gfx950 kernels and C ABI of the coupled double-distribution-
+// function thermal lattice Boltzmann model on D2Q9 (Li, Luo, He, Gao & Tao).
+//
+// Design (MI355X / CDNA4):
+//  * Structure-of-arrays populations, 18 planes (f^ then h-) per buffer, two
+//    buffers (A/B).  A buffer holds the post-collision values of the previous
+//    step at each node's own index; a step pull-gathers them (Eq. 45 read
+//    backwards), collides, and stores into the other buffer at the node's own
+//    index, so every load and store of a wavefront touches 64 consecutive
+//    nodes of one plane.
+//  * Deviation storage and arithmetic: a plane holds x - x_rest, where x_rest
+//    is the equilibrium of the rest state (rho0, 0, T0).  Moments, equilibria,
+//    the collision and the codec all work on these deviations, which keeps
+//    FP32 (and the 16-bit codecs) accurate for the small perturbations of
+//    low-Mach flows.
+//  * One wavefront owns a strip of 62 columns x R rows and marches up the
+//    strip.  Lanes 0 and 63 are halo columns; the x-neighbours of the
+//    correction term's Q (Eq. 48-50) come from the adjacent lanes, the
+//    y-neighbours from the previous and the look-ahead row kept in registers,
+//    so no LDS and no barrier is needed and each row is gathered once.
+//  * Boundary nodes gather the populations of the interior node they
+//    extrapolate from instead of their own (non-equilibrium extrapolation),
+//    so the wavefront's loads stay uniform; the rebuild is a short divergent
+//    branch on boundary lanes only.
+//  * Work is swizzled over the 8 XCDs so that neighbouring strips, which
+//    share halo rows and columns, run on the same L2.
+//  * MFMA is not used: the step is a bandwidth-bound stencil, not a dense
+//    contraction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbddf.h"
+
+namespace {
+
+constexpr int kWave = 64;
+constexpr int kTile = 62;  // owned columns per wavefront
+constexpr int kBlock = 256;
+constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kRedBlocks = 1024;
+constexpr int kNred = 8;
+constexpr int kPlanePad = 320;  // elements appended to each plane (64-aligned)
+
+enum : int { K_INTERIOR = 0, K_DIRICHLET = 1, K_ADIABATIC = 2, K_INLET = 3, K_OUTLET = 4 };
+
+// Everything a kernel needs, passed by value.
+struct KArgs {
+    int nx, ny, pitch;
+    int tiles_x, n_strips, strip_rows;
+    int per_x, per_y;
+    long long plane_bytes;
+    int total, heat, corr, coupled, bgk, visc, rho_press, has_force;
+    float rho0, E0, inv_E0, half_g, g, Pr;
+    // relaxation for a constant tau_f
+    float s_nu, s_e, s_z, s_q, s_rho, s_j, omega_h, kcoup;
+    int tie_e, tie_z;
+    // viscosity laws: mu3 = 3 mu_ref, r = cT theta = T / T_ref
+    float mu3, cT, visc_n, sT;
+    // sides x-, x+, y-, y+
+    int side_kind[4];
+    float side_ux[4], side_uy[4], side_dth[4];
+    // inlet state at the launch's time step
+    float in_drho, in_ux, in_dth;
+};
+
+// Reciprocal: hardware estimate plus one Newton step, so that rho * (j / rho)
+// reproduces j without the systematic bias of the raw estimate.
+__device__ __forceinline__ float frcp(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.f), r);
+}
+
+// ------------------------------------------------------------------ storage
+template <int ST> struct Codec;
+// q is the plane (0..17); after unrolling it is a compile-time constant.
+template <> struct Codec<LB_STORE_F32> {
+    typedef float T;
+    static __device__ __forceinline__ float ld(const T *p, unsigned i, int) { return p[i]; }
+    static __device__ __forceinline__ void st(T *p, unsigned i, float v, int) { p[i] = v; }
+};
+// FP16 keeps deviation * 2^(8 + k_a), k_a = 1, 3, 5 for the rest, axis and
+// diagonal velocities (about 1 / w_a): every plane then spans the same
+// range, far above the FP16 subnormals and far below its maximum.  Powers of
+// two make the scaling exact.
+__device__ __forceinline__ float f16_scale(int q) {
+    const int a = q % 9;
+    return a == 0 ? 512.f : (a < 5 ? 2048.f : 8192.f);
+}
+template <> struct Codec<LB_STORE_F16> {
+    typedef _Float16 T;
+    static __device__ __forceinline__ float ld(const T *p, unsigned i, int q) { return (float)p[i] * (1.f / f16_scale(q)); }
+    static __device__ __forceinline__ void st(T *p, unsigned i, float v, int q) { p[i] = (_Float16)(v * f16_scale(q)); }
+};
+template <> struct Codec<LB_STORE_BF16> {
+    typedef unsigned short T;
+    static __device__ __forceinline__ float ld(const T *p, unsigned i, int) { return __uint_as_float(((unsigned)p[i]) << 16); }
+    static __device__ __forceinline__ void st(T *p, unsigned i, float v, int) {
+        // round to nearest even
+        unsigned u = __float_as_uint(v);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        p[i] = (unsigned short)(u >> 16);
+    }
+};
+
+template <int ST>
+__device__ __forceinline__ const typename Codec<ST>::T *cplane(const char *base, long long pb, int q) {
+    return reinterpret_cast<const typename Codec<ST>::T *>(base + (long long)q * pb);
+}
+template <int ST>
+__device__ __forceinline__ typename Codec<ST>::T *wplane(char *base, long long pb, int q) {
+    return reinterpret_cast<typename Codec<ST>::T *>(base + (long long)q * pb);
+}
+
+// --------------------------------------------------------- node primitives
+// drho = rho - rho0, j = rho u (the momentum of Eq. 46 with the forcing note),
+// u, dth = theta - 1; sf, sx, sy are the raw sums sum f, sum e f of the
+// (possibly rebuilt) populations, which equal drho, jx and jy + rho g / 2 on
+// interior nodes.
+struct Mom {
+    float drho, rho, jx, jy, ux, uy, dth, sf, sx, sy;
+};
+
+// Pull-gather (Eq. 45): population a of node (x, y) is the post-collision
+// value stored at (x, y) - e_a, with periodic wrap.  Sources of a bounded
+// axis are interior nodes, so their neighbours never leave the domain.
+template <int ST>
+__device__ __forceinline__ void gather(const KArgs &a, const char *__restrict__ src, int x, int y, float d[18]) {
+    int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
+    xm += (xm < 0) ? a.nx : 0;
+    xp -= (xp >= a.nx) ? a.nx : 0;
+    ym += (ym < 0) ? a.ny : 0;
+    yp -= (yp >= a.ny) ? a.ny : 0;
+    const unsigned rm = (unsigned)ym * a.pitch, rc = (unsigned)y * a.pitch, rp = (unsigned)yp * a.pitch;
+    const unsigned o[9] = {rc + x, rc + xm, rm + x, rc + xp, rp + x, rm + xm, rm + xp, rp + xp, rp + xm};
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        d[q] = Codec<ST>::ld(cplane<ST>(src, a.plane_bytes, q), o[q], q);
+        d[9 + q] = Codec<ST>::ld(cplane<ST>(src, a.plane_bytes, 9 + q), o[q], 9 + q);
+    }
+}
+
+// Eq. 46 with the forcing note (rho u = sum e f + a/2, a = (0, -rho g)) and
+// Eq. 37 / the internal-energy form, written for deviations from rest.
+__device__ __forceinline__ Mom moments(const KArgs &a, const float d[18]) {
+    Mom m;
+    const float s1 = (d[1] + d[3]) + (d[2] + d[4]);
+    const float s2 = (d[5] + d[7]) + (d[6] + d[8]);
+    m.drho = d[0] + (s1 + s2);
+    const float jx = (d[1] - d[3]) + (d[5] - d[7]) + (d[8] - d[6]);
+    const float jy = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
+    m.sf = m.drho;
+    m.sx = jx;
+    m.sy = jy;
+    m.rho = a.rho0 + m.drho;
+    const float ir = frcp(m.rho);
+    m.jx = jx;
+    m.jy = jy - a.half_g * m.rho;
+    m.ux = m.jx * ir;
+    m.uy = m.jy * ir;
+    const float sh = ((d[9] + d[10]) + (d[11] + d[12])) + ((d[13] + d[14]) + (d[15] + d[16])) + d[17];
+    const float e = (sh - m.drho * a.E0) * ir;  // E - E0 (total) or (rho E_int - rho E0)/rho
+    m.dth = a.total ? (e - 0.5f * (m.ux * m.ux + m.uy * m.uy)) * a.inv_E0 : e * a.inv_E0;
+    return m;
+}
+
+// Deviations of the equilibria Eq. 18a and Eq. 18b (or h = b R T f / 2) from
+// the rest equilibria, lattice units (R T0 = 1/3), written with the momentum
+// j = rho u so that the first moment of f_eq is j itself:
+//   f_eq - f_rest = w [drho + c rho th - 1.5 j.u + (e.j)(B + 4.5 e.u)],
+//   c = -1, 1/2, 2 and B = 3, 3 - 1.5 th, 3 + 3 th for |e|^2 = 0, 1, 2.
+__device__ __forceinline__ void equilibria(const KArgs &a, const Mom &m, float fe[9], float he[9]) {
+    const float w0 = 4.f / 9.f, w1 = 1.f / 9.f, w2 = 1.f / 36.f;
+    const float th = a.coupled ? m.dth : 0.f;  // theta_eq - 1
+    const float ux = m.ux, uy = m.uy, jx = m.jx, jy = m.jy, drho = m.drho, rho = m.rho;
+    const float ju = jx * ux + jy * uy;
+    const float base = drho - 1.5f * ju;
+    const float rth = rho * th;
+    const float A0 = base - rth, A1 = base + 0.5f * rth, A2 = base + 2.f * rth;
+    const float B1 = 3.f - 1.5f * th, B2 = 3.f + 3.f * th;
+    const float v5 = ux + uy, v6 = uy - ux, j5 = jx + jy, j6 = jy - jx;
+    fe[0] = w0 * A0;
+    fe[1] = w1 * (A1 + jx * (B1 + 4.5f * ux));
+    fe[3] = w1 * (A1 - jx * (B1 - 4.5f * ux));
+    fe[2] = w1 * (A1 + jy * (B1 + 4.5f * uy));
+    fe[4] = w1 * (A1 - jy * (B1 - 4.5f * uy));
+    fe[5] = w2 * (A2 + j5 * (B2 + 4.5f * v5));
+    fe[7] = w2 * (A2 - j5 * (B2 - 4.5f * v5));
+    fe[6] = w2 * (A2 + j6 * (B2 + 4.5f * v6));
+    fe[8] = w2 * (A2 - j6 * (B2 - 4.5f * v6));
+    const float u2 = ux * ux + uy * uy;
+    if (a.total) {
+        // h_eq - h_rest = w [rho0 (E - E0) + c (p theta - p0) + p (3 eu + 9 eu^2 - 3 u^2)] + E (f_eq - f_rest),
+        // p (3 eu + 9 eu^2 - 3 u^2) = theta [(e.j)(1 + 3 e.u) - j.u] with p = rho theta / 3
+        const float E = a.E0 * (1.f + m.dth) + 0.5f * u2;
+        const float K0 = a.rho0 * (a.E0 * m.dth + 0.5f * u2);
+        const float third = 1.f / 3.f;
+        const float Pt = 1.f + th;
+        const float Pd = (drho + rth * (2.f + th)) * third;
+        const float k0 = K0 - Pd - Pt * ju, k1 = K0 + 0.5f * Pd - Pt * ju, k2 = K0 + 2.f * Pd - Pt * ju;
+        he[0] = w0 * k0 + E * fe[0];
+        he[1] = w1 * (k1 + Pt * jx * (1.f + 3.f * ux)) + E * fe[1];
+        he[3] = w1 * (k1 - Pt * jx * (1.f - 3.f * ux)) + E * fe[3];
+        he[2] = w1 * (k1 + Pt * jy * (1.f + 3.f * uy)) + E * fe[2];
+        he[4] = w1 * (k1 - Pt * jy * (1.f - 3.f * uy)) + E * fe[4];
+        he[5] = w2 * (k2 + Pt * j5 * (1.f + 3.f * v5)) + E * fe[5];
+        he[7] = w2 * (k2 - Pt * j5 * (1.f - 3.f * v5)) + E * fe[7];
+        he[6] = w2 * (k2 + Pt * j6 * (1.f + 3.f * v6)) + E * fe[6];
+        he[8] = w2 * (k2 - Pt * j6 * (1.f - 3.f * v6)) + E * fe[8];
+    } else {
+        const float c = a.rho0 * a.E0 * m.dth, Et = a.E0 * (1.f + m.dth);
+        he[0] = w0 * c + Et * fe[0];
+#pragma unroll
+        for (int q = 1; q < 5; ++q) he[q] = w1 * c + Et * fe[q];
+#pragma unroll
+        for (int q = 5; q < 9; ++q) he[q] = w2 * c + Et * fe[q];
+    }
+}
+
+struct Relax {
+    float s_nu, s_e, s_z, omega_h, kcoup;
+};
+
+// Per-node transport: tau_f = mu(T) / p + 1/2 (Sec. IV-C) for the viscosity
+// laws, tau_h = (tau_f - 1/2)/Pr, omega_h = 2/(2 tau_h + 1),
+// coupling factor (1 - omega_h/2)(Pr - 1)/tau_f (Eq. 47).
+__device__ __forceinline__ Relax transport(const KArgs &a, float rho, float dth) {
+    Relax t;
+    if (a.visc == LB_VISC_CONST_TAU) {
+        t.s_nu = a.s_nu;
+        t.s_e = a.s_e;
+        t.s_z = a.s_z;
+        t.omega_h = a.omega_h;
+        t.kcoup = a.kcoup;
+        return t;
+    }
+    const float th = 1.f + dth;
+    float mu3 = a.mu3;
+    if (a.visc == LB_VISC_POWER) {
+        mu3 *= exp2f(a.visc_n * log2f(a.cT * th));
+    } else if (a.visc == LB_VISC_SUTHERLAND) {
+        const float r = a.cT * th;
+        mu3 *= r * sqrtf(r) * (1.f + a.sT) * frcp(r + a.sT);
+    }
+    const float tau = mu3 * frcp(rho * th) + 0.5f;  // p = rho R T = rho theta / 3
+    t.s_nu = frcp(tau);
+    t.omega_h = 2.f * a.Pr * frcp(2.f * tau - 1.f + a.Pr);
+    t.kcoup = (1.f - 0.5f * t.omega_h) * (a.Pr - 1.f) * t.s_nu;
+    t.s_e = a.tie_e ? t.s_nu : a.s_e;
+    t.s_z = a.tie_z ? t.s_nu : a.s_z;
+    return t;
+}
+
+// Node kind and the node a boundary node extrapolates from (inward normal,
+// the diagonal at corners), for the node (x, y) of the domain.
+struct BInfo {
+    int kind, fx, fy;
+    float ux, uy, dth;
+};
+
+__device__ __forceinline__ BInfo classify(const KArgs &a, int x, int y) {
+    BInfo b;
+    b.kind = K_INTERIOR;
+    b.fx = x;
+    b.fy = y;
+    b.ux = b.uy = b.dth = 0.f;
+    int hx = -1, hy = -1;
+    if (!a.per_x) {
+        if (x == 0) hx = 0;
+        else if (x == a.nx - 1) hx = 1;
+    }
+    if (!a.per_y) {
+        if (y == 0) hy = 2;
+        else if (y == a.ny - 1) hy = 3;
+    }
+    if (hx < 0 && hy < 0) return b;
+    if (hx >= 0) b.fx = (hx == 0) ? 1 : a.nx - 2;
+    if (hy >= 0) b.fy = (hy == 2) ? 1 : a.ny - 2;
+    if (hx >= 0 && hy >= 0) {
+        b.ux = a.side_ux[hx];
+        b.uy = a.side_uy[hx];
+        if (a.side_kind[hx] == LB_BC_WALL) {
+            b.kind = K_DIRICHLET;
+            b.dth = a.side_dth[hx];
+        } else if (a.side_kind[hy] == LB_BC_WALL) {
+            b.kind = K_DIRICHLET;
+            b.dth = a.side_dth[hy];
+        } else {
+            b.kind = K_ADIABATIC;
+        }
+        return b;
+    }
+    const int s = hx >= 0 ? hx : hy;
+    const int k = a.side_kind[s];
+    b.ux = a.side_ux[s];
+    b.uy = a.side_uy[s];
+    b.dth = a.side_dth[s];
+    b.kind = (k == LB_BC_WALL) ? K_DIRICHLET : (k == LB_BC_ADIABATIC) ? K_ADIABATIC : (k == LB_BC_INLET) ? K_INLET : K_OUTLET;
+    return b;
+}
+
+// State of node (x, y) at the current time after the boundary treatment:
+// deviations d[18], moments, kind.
+template <int ST, bool BC>
+__device__ __forceinline__ int node_state(const KArgs &a, const char *__restrict__ src, int x, int y, float d[18], Mom &m) {
+    if (!BC) {
+        gather<ST>(a, src, x, y, d);
+        m = moments(a, d);
+        return K_INTERIOR;
+    }
+    const BInfo b = classify(a, x, y);
+    gather<ST>(a, src, b.fx, b.fy, d);
+    m = moments(a, d);
+    if (b.kind == K_INTERIOR || b.kind == K_OUTLET) return b.kind;  // outlet: exact copy of the neighbour
+    Mom mb;
+    if (b.kind == K_INLET) {
+        mb.drho = a.in_drho;
+        mb.ux = a.in_ux;
+        mb.uy = 0.f;
+        mb.dth = a.in_dth;
+        mb.rho = a.rho0 + mb.drho;
+        mb.jx = mb.rho * mb.ux;
+        mb.jy = 0.f;
+        float he[9];
+        equilibria(a, mb, d, he);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) d[9 + q] = he[q];
+        const Mom raw = moments(a, d);
+        mb.sf = raw.sf;
+        mb.sx = raw.sx;
+        mb.sy = raw.sy;
+        m = mb;
+        return K_INLET;
+    }
+    mb.ux = b.ux;
+    mb.uy = b.uy;
+    if (b.kind == K_DIRICHLET) {
+        mb.dth = b.dth;
+    } else {
+        // T_b = (4 T_1 - T_2) / 3 along the inward normal
+        float d2[18];
+        gather<ST>(a, src, 2 * b.fx - x, 2 * b.fy - y, d2);
+        const Mom m2 = moments(a, d2);
+        mb.dth = (4.f * m.dth - m2.dth) * (1.f / 3.f);
+    }
+    // pressure extrapolation rho_b T_b = rho_f T_f, or rho_b = rho_f
+    mb.drho = a.rho_press ? m.drho + m.rho * (m.dth - mb.dth) * frcp(1.f + mb.dth) : m.drho;
+    mb.rho = a.rho0 + mb.drho;
+    mb.jx = mb.rho * mb.ux;
+    mb.jy = mb.rho * mb.uy;
+    float fb[9], hb[9], ff[9], hf[9];
+    equilibria(a, mb, fb, hb);
+    equilibria(a, m, ff, hf);
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        d[q] += fb[q] - ff[q];
+        d[9 + q] += hb[q] - hf[q];
+    }
+    const Mom raw = moments(a, d);
+    mb.sf = raw.sf;
+    mb.sx = raw.sx;
+    mb.sy = raw.sy;
+    m = mb;
+    return b.kind;
+}
+
+// Collision of one node (Eq. 44 or Eq. 34 for f^, Eq. 47 or Eq. 38 for h-),
+// deviations in d, results in o.
+__device__ __forceinline__ void collide(const KArgs &a, const float d[18], const Mom &m, int kind, float phix,
+                                        float phiy, float o[18]) {
+    float fe[9], he[9];
+    equilibria(a, m, fe, he);
+    if (kind == K_INLET) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            o[q] = fe[q];
+            o[9 + q] = he[q];
+        }
+        return;
+    }
+    const Relax t = transport(a, m.rho, m.dth);
+    const float ux = m.ux, uy = m.uy;
+    const float ay = -m.rho * a.g;
+    // velocity-space sources C = M^-1 (C^ + F^): Eq. 49 plus the forcing term
+    const float w0 = 4.f / 9.f, w1 = 1.f / 9.f, w2 = 1.f / 36.f;
+    float C[9];
+    {
+        const float cx0 = -phix * (1.f / 9.f), cx1 = -phix * (1.f / 36.f), cx2 = phix * (1.f / 18.f);
+        const float cy = 0.25f * phiy;
+        C[0] = cx0;
+        C[1] = C[3] = cx1 + cy;
+        C[2] = C[4] = cx1 - cy;
+        C[5] = C[6] = C[7] = C[8] = cx2;
+        if (a.has_force) {
+            const float f3 = -3.f * uy * ay;
+            C[0] += w0 * f3;
+            C[1] += w1 * f3;
+            C[3] += w1 * f3;
+            C[2] += w1 * ay * (3.f + 6.f * uy);
+            C[4] += w1 * ay * (-3.f + 6.f * uy);
+            C[5] += w2 * ay * (3.f + 9.f * ux + 6.f * uy);
+            C[6] += w2 * ay * (3.f - 9.f * ux + 6.f * uy);
+            C[7] += w2 * ay * (-3.f + 9.f * ux + 6.f * uy);
+            C[8] += w2 * ay * (-3.f - 9.f * ux + 6.f * uy);
+        }
+    }
+    {
+        // BGK (Eq. 34) is the MRT scheme with every rate equal to 1/tau_f, so both
+        // run through the same moment-space increments.
+        const float sr = a.bgk ? t.s_nu : a.s_rho, sj = a.bgk ? t.s_nu : a.s_j;
+        const float se = a.bgk ? t.s_nu : t.s_e, sz = a.bgk ? t.s_nu : t.s_z, sq = a.bgk ? t.s_nu : a.s_q;
+        // moments of the deviations, m = M f (Eq. B1); the conserved ones are
+        // the raw sums, so that their increments vanish exactly on interior nodes
+        const float s1 = (d[1] + d[3]) + (d[2] + d[4]);
+        const float s2 = (d[5] + d[7]) + (d[6] + d[8]);
+        const float dx13 = d[1] - d[3], dy24 = d[2] - d[4];
+        const float a57 = d[5] - d[7], a86 = d[8] - d[6], a68 = d[6] - d[8];
+        const float m1 = -4.f * d[0] - s1 + 2.f * s2;
+        const float m2 = 4.f * d[0] - 2.f * s1 + s2;
+        const float m4 = -2.f * dx13 + (a57 + a86);
+        const float m6 = -2.f * dy24 + (a57 + a68);
+        const float m7 = (d[1] + d[3]) - (d[2] + d[4]);
+        const float m8 = (d[5] + d[7]) - (d[6] + d[8]);
+        // equilibria Eq. 41 minus M f_rest
+        const float thE = a.coupled ? m.dth : 0.f;
+        const float rho = m.rho;
+        const float qq = 3.f * (m.jx * ux + m.jy * uy) + 2.f * rho * thE;
+        const float e1 = -2.f * m.drho + qq, e2 = m.drho - qq;
+        const float e4 = -m.jx * (1.f - thE), e6 = -m.jy * (1.f - thE);
+        const float e7 = m.jx * ux - m.jy * uy, e8 = m.jx * uy;
+        // sources C^ = (0, phi_x, 0, 0, 0, 0, 0, phi_y, 0) + F^ (Eq. 48, 51)
+        const float uay = uy * ay;
+        const float c1 = phix + 6.f * uay, c2 = -6.f * uay, c5 = ay, c6 = -ay, c7 = phiy - 2.f * uay, c8 = ux * ay;
+        // Eq. 44 as increments dm = m* - m
+        const float g0 = -sr * (m.sf - m.drho);
+        const float g1 = -se * (m1 - e1) + (1.f - 0.5f * se) * c1;
+        const float g2 = -sz * (m2 - e2) + (1.f - 0.5f * sz) * c2;
+        const float g3 = -sj * (m.sx - m.jx);
+        const float g4 = -sq * (m4 - e4);
+        const float g5 = -sj * (m.sy - m.jy) + (1.f - 0.5f * sj) * c5;
+        const float g6 = -sq * (m6 - e6) + (1.f - 0.5f * sq) * c6;
+        const float g7 = -t.s_nu * (m7 - e7) + (1.f - 0.5f * t.s_nu) * c7;
+        const float g8 = -t.s_nu * (m8 - e8) + (1.f - 0.5f * t.s_nu) * c8;
+        // f* = f + M^-1 dm (Eq. B2)
+        const float A = g0 * (1.f / 9.f);
+        const float a1 = A - g1 * (1.f / 36.f) - g2 * (1.f / 18.f);
+        const float a2 = A + g1 * (1.f / 18.f) + g2 * (1.f / 36.f);
+        const float X = (g3 - g4) * (1.f / 6.f), Y = (g5 - g6) * (1.f / 6.f), P = 0.25f * g7;
+        const float X2 = g3 * (1.f / 6.f) + g4 * (1.f / 12.f), Y2 = g5 * (1.f / 6.f) + g6 * (1.f / 12.f);
+        const float Pxy = 0.25f * g8;
+        o[0] = d[0] + (A + (g2 - g1) * (1.f / 9.f));
+        o[1] = d[1] + (a1 + X + P);
+        o[3] = d[3] + (a1 - X + P);
+        o[2] = d[2] + (a1 + Y - P);
+        o[4] = d[4] + (a1 - Y - P);
+        o[5] = d[5] + (a2 + X2 + Y2 + Pxy);
+        o[6] = d[6] + (a2 - X2 + Y2 - Pxy);
+        o[7] = d[7] + (a2 - X2 - Y2 + Pxy);
+        o[8] = d[8] + (a2 + X2 - Y2 - Pxy);
+    }
+    // h: BGK plus the coupling term (1 - omega_h/2)(Z/tau_hf)(f - f_eq + C/2), Z = e.u
+    const float wh = t.omega_h;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) o[9 + q] = d[9 + q] - wh * (d[9 + q] - he[q]);
+    if (a.heat) {
+        const float k = t.kcoup;
+        const float v5 = ux + uy, v6 = uy - ux;
+        const float z[9] = {0.f, ux, uy, -ux, -uy, v5, v6, -v5, -v6};
+#pragma unroll
+        for (int q = 1; q < 9; ++q) o[9 + q] += k * z[q] * (d[q] - fe[q] + 0.5f * C[q]);
+    }
+}
+
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+    const int xcd = b & 7, idx = b >> 3, per = nb >> 3, rem = nb & 7;
+    return xcd * per + min(xcd, rem) + idx;
+}
+
+// Row state of the lane's column for row y of the marching strip (y may be
+// -1 or ny): deviations, moments, kind, and Q = rho u (1 - theta) (Eq. 48),
+// zero outside the domain of a bounded axis.
+template <int ST, bool BC>
+__device__ __forceinline__ int row_state(const KArgs &a, const char *__restrict__ src, int xw, bool xin, int y,
+                                         float d[18], Mom &m, float &Qx, float &Qy) {
+    int yw;
+    bool yin;
+    if (a.per_y) {
+        yw = y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
+        yin = true;
+    } else {
+        yin = (y >= 0) && (y < a.ny);
+        yw = min(max(y, 0), a.ny - 1);
+    }
+    const int kind = node_state<ST, BC>(a, src, xw, yw, d, m);
+    const float mq = (a.corr && xin && yin) ? -m.rho * m.dth : 0.f;
+    Qx = mq * m.ux;
+    Qy = mq * m.uy;
+    return kind;
+}
+
+// ----------------------------------------------------------------- kernels
+template <int ST, bool BC>
+__global__ __launch_bounds__(kBlock) void k_step(const KArgs a, const char *__restrict__ src, char *__restrict__ dst) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int wv = blk * kWavesPerBlock + (threadIdx.x >> 6);
+    if (wv >= a.tiles_x * a.n_strips) return;
+    const int tx = wv % a.tiles_x, sy = wv / a.tiles_x;
+    const int gx = tx * kTile - 1 + lane;
+    int xw;
+    bool xin;
+    if (a.per_x) {
+        xw = gx % a.nx;
+        xw += (xw < 0) ? a.nx : 0;
+        xin = true;
+    } else {
+        xin = (gx >= 0) && (gx < a.nx);
+        xw = min(max(gx, 0), a.nx - 1);
+    }
+    const bool owned = (lane >= 1) && (lane <= kTile) && (gx < a.nx);
+    const int y0 = sy * a.strip_rows;
+    const int y1 = min(y0 + a.strip_rows, a.ny);
+
+    float dc[18], dn[18];
+    Mom mc, mn;
+    float qxp, qyp, qxc, qyc, qxn, qyn;
+    row_state<ST, BC>(a, src, xw, xin, y0 - 1, dc, mc, qxp, qyp);
+    int kc = row_state<ST, BC>(a, src, xw, xin, y0, dc, mc, qxc, qyc);
+    for (int y = y0; y < y1; ++y) {
+        const int kn = row_state<ST, BC>(a, src, xw, xin, y + 1, dn, mn, qxn, qyn);
+        // Eq. 50: central differences of Q, x-neighbours from the adjacent lanes
+        const float qxl = __shfl_up(qxc, 1), qxr = __shfl_down(qxc, 1);
+        const float dQx = 0.5f * (qxr - qxl), dQy = 0.5f * (qyn - qyp);
+        float phix = 3.f * (dQx + dQy), phiy = dQx - dQy;
+        if (BC && kc != K_INTERIOR) phix = phiy = 0.f;
+        float o[18];
+        collide(a, dc, mc, kc, phix, phiy, o);
+        if (owned) {
+            const unsigned idx = (unsigned)y * a.pitch + xw;
+#pragma unroll
+            for (int q = 0; q < 18; ++q) Codec<ST>::st(wplane<ST>(dst, a.plane_bytes, q), idx, o[q], q);
+        }
+        qxp = qxc;
+        qyp = qyc;
+        qxc = qxn;
+        qyc = qyn;
+#pragma unroll
+        for (int q = 0; q < 18; ++q) dc[q] = dn[q];
+        mc = mn;
+        kc = kn;
+    }
+}
+
+// Initial state: the pull of the first step must see the equilibria of the
+// fields, so node (x, y) writes its equilibria to (x, y) - e_a.
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_init(const KArgs a, const float *__restrict__ fields, long long fplane,
+                                                 char *__restrict__ dst) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.nx * a.ny) return;
+    const int x = i % a.nx, y = i / a.nx;
+    const unsigned k = (unsigned)y * a.pitch + x;
+    Mom m;
+    m.drho = fields[k];
+    m.ux = fields[fplane + k];
+    m.uy = fields[2 * fplane + k];
+    m.dth = fields[3 * fplane + k];
+    m.rho = a.rho0 + m.drho;
+    m.jx = m.rho * m.ux;
+    m.jy = m.rho * m.uy;
+    m.sf = m.sx = m.sy = 0.f;
+    float fe[9], he[9];
+    equilibria(a, m, fe, he);
+    const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+    const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        int tx = x - ex[q], ty = y - ey[q];
+        if (tx < 0 || tx >= a.nx) {
+            if (!a.per_x) continue;
+            tx += (tx < 0) ? a.nx : -a.nx;
+        }
+        if (ty < 0 || ty >= a.ny) {
+            if (!a.per_y) continue;
+            ty += (ty < 0) ? a.ny : -a.ny;
+        }
+        const unsigned t = (unsigned)ty * a.pitch + tx;
+        Codec<ST>::st(wplane<ST>(dst, a.plane_bytes, q), t, fe[q], q);
+        Codec<ST>::st(wplane<ST>(dst, a.plane_bytes, 9 + q), t, he[q], 9 + q);
+    }
+}
+
+// Moments (deviations drho, ux, uy, dtheta) after the boundary treatment.
+// full != 0 writes rho and T = T0 theta with T0 = tscale instead.
+template <int ST, bool BC>
+__global__ __launch_bounds__(kBlock) void k_macros(const KArgs a, const char *__restrict__ src, float *__restrict__ o0,
+                                                   float *__restrict__ o1, float *__restrict__ o2,
+                                                   float *__restrict__ o3, int opitch, int full, float tscale) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.nx * a.ny) return;
+    const int x = i % a.nx, y = i / a.nx;
+    float d[18];
+    Mom m;
+    node_state<ST, BC>(a, src, x, y, d, m);
+    const unsigned k = (unsigned)y * opitch + x;
+    if (o0) o0[k] = full ? m.rho : m.drho;
+    if (o1) o1[k] = m.ux;
+    if (o2) o2[k] = m.uy;
+    if (o3) o3[k] = full ? tscale * (1.f + m.dth) : m.dth;
+}
+
+// Population deviations after the boundary treatment, planes q0 .. q0+nq-1.
+template <int ST, bool BC>
+__global__ __launch_bounds__(kBlock) void k_pops(const KArgs a, const char *__restrict__ src, float *__restrict__ out,
+                                                 long long oplane, int q0, int nq) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= a.nx * a.ny) return;
+    const int x = i % a.nx, y = i / a.nx;
+    float d[18];
+    Mom m;
+    node_state<ST, BC>(a, src, x, y, d, m);
+    const unsigned k = (unsigned)y * a.pitch + x;
+#pragma unroll
+    for (int q = 0; q < 18; ++q)
+        if (q >= q0 && q < q0 + nq) out[(q - q0) * oplane + k] = d[q];
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+// FP64 sums over the grid: [sum d_f, sum d_h, sum e_x d_f, sum e_y d_f, #bad,
+// sum (dth - snap)^2, sum (1 + dth)^2, 0] as per-block partials.
+template <int ST, bool BC>
+__global__ __launch_bounds__(kBlock) void k_diag(const KArgs a, const char *__restrict__ src, float *__restrict__ snap,
+                                                 int use_snap, int write_snap, double *__restrict__ partials) {
+    double acc[kNred] = {0, 0, 0, 0, 0, 0, 0, 0};
+    const int n = a.nx * a.ny;
+    for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
+        const int x = i % a.nx, y = i / a.nx;
+        float d[18];
+        Mom m;
+        node_state<ST, BC>(a, src, x, y, d, m);
+        double sf = 0, sh = 0;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            sf += (double)d[q];
+            sh += (double)d[9 + q];
+        }
+        acc[0] += sf;
+        acc[1] += sh;
+        acc[2] += ((double)d[1] - d[3]) + ((double)d[5] - d[6]) + ((double)d[8] - d[7]);
+        acc[3] += ((double)d[2] - d[4]) + ((double)d[5] + d[6]) - ((double)d[7] + d[8]);
+        const bool ok = isfinite(m.rho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(m.dth) && m.rho > 0.f &&
+                        (1.f + m.dth) > 0.f;
+        acc[4] += ok ? 0.0 : 1.0;
+        const unsigned k = (unsigned)y * a.pitch + x;
+        if (use_snap) {
+            const double e = (double)m.dth - (double)snap[k];
+            acc[5] += e * e;
+        }
+        const double t = 1.0 + (double)m.dth;
+        acc[6] += t * t;
+        if (write_snap) snap[k] = m.dth;
+    }
+    __shared__ double red[kNred][kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kNred; ++j) {
+        const double v = wave_sum(acc[j]);
+        if (lane == 0) red[j][w] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNred) {
+        double s = 0;
+        for (int j = 0; j < kWavesPerBlock; ++j) s += red[threadIdx.x][j];
+        partials[blockIdx.x * kNred + threadIdx.x] = s;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_final(const double *__restrict__ partials, int nblocks,
+                                                         double *__restrict__ out) {
+    __shared__ double red[kNred][kWavesPerBlock];
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
+    for (int j = 0; j < kNred; ++j) {
+        double s = 0;
+        for (int b = threadIdx.x; b < nblocks; b += kBlock) s += partials[b * kNred + j];
+        s = wave_sum(s);
+        if (lane == 0) red[j][w] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNred) {
+        double s = 0;
+        for (int j = 0; j < kWavesPerBlock; ++j) s += red[threadIdx.x][j];
+        out[threadIdx.x] = s;
+    }
+}
+
+// ------------------------------------------------------------- host side
+thread_local std::string g_err;
+
+lb_status fail(lb_status s, const std::string &msg) {
+    g_err = msg;
+    return s;
+}
+
+#define HIPCHK(call)                                                                                   \
+    do {                                                                                               \
+        hipError_t e_ = (call);                                                                        \
+        if (e_ != hipSuccess) return fail(LB_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Layout {
+    int pitch;
+    size_t plane_elems, plane_bytes, pops_bytes, snap_off, snap_bytes, part_off, red_off, total;
+    int ssize;
+};
+
+Layout layout_of(const lb_params *p) {
+    Layout L;
+    L.ssize = p->storage == LB_STORE_F32 ? 4 : 2;
+    L.pitch = (int)align_up((size_t)p->nx, 64);
+    L.plane_elems = (size_t)L.pitch * p->ny + kPlanePad;
+    L.plane_bytes = L.plane_elems * L.ssize;
+    L.pops_bytes = align_up(18 * L.plane_bytes, 256);
+    L.snap_off = 2 * L.pops_bytes;
+    L.snap_bytes = align_up((size_t)L.pitch * p->ny * sizeof(float), 256);
+    L.part_off = L.snap_off + L.snap_bytes;
+    L.red_off = L.part_off + align_up(kRedBlocks * kNred * sizeof(double), 256);
+    L.total = L.red_off + 256;
+    return L;
+}
+
+bool side_bounded(int k) { return k != LB_BC_PERIODIC; }
+
+lb_status validate(const lb_params *p) {
+    if (!p) return fail(LB_EINVAL, "null parameters");
+    if (p->nx < 1 || p->ny < 1) return fail(LB_EINVAL, "nx and ny must be >= 1");
+    if ((double)align_up((size_t)p->nx, 64) * p->ny > (double)(1u << 28))
+        return fail(LB_EINVAL, "grid too large (more than 2^28 nodes per plane)");
+    if (p->storage < 0 || p->storage > 2) return fail(LB_EINVAL, "storage");
+    if (p->energy < 0 || p->energy > 1) return fail(LB_EINVAL, "energy");
+    if (p->collision < 0 || p->collision > 1) return fail(LB_EINVAL, "collision");
+    if (p->visc < 0 || p->visc > 3) return fail(LB_EINVAL, "visc");
+    if (p->rho_extrap < 0 || p->rho_extrap > 1) return fail(LB_EINVAL, "rho_extrap");
+    if (!(p->rho0 > 0) || !(p->T0 > 0) || !(p->b > 0) || !(p->Pr > 0))
+        return fail(LB_EINVAL, "rho0, T0, b and Pr must be positive");
+    if (!(std::fabs(3.0 * p->R * p->T0 - 1.0) <= 1e-12)) return fail(LB_EINVAL, "lattice units need R*T0 = 1/3 (c = 1)");
+    if (p->energy == LB_ENERGY_INTERNAL && p->heating)
+        return fail(LB_EINVAL, "the heating term belongs to the total-energy form");
+    if (p->visc == LB_VISC_CONST_TAU) {
+        if (!(p->tau_f > 0.5)) return fail(LB_EINVAL, "tau_f must exceed 1/2");
+    } else if (!(p->mu_ref > 0) || !(p->T_ref > 0)) {
+        return fail(LB_EINVAL, "mu_ref and T_ref must be positive");
+    }
+    if (p->visc == LB_VISC_SUTHERLAND && !(p->suth_S >= 0)) return fail(LB_EINVAL, "suth_S must be >= 0");
+    if (p->s_e > 0 && !(p->s_e < 2)) return fail(LB_EINVAL, "s_e must lie in (0, 2)");
+    if (p->s_zeta > 0 && !(p->s_zeta < 2)) return fail(LB_EINVAL, "s_zeta must lie in (0, 2)");
+    if (!(p->s_q > 0 && p->s_q < 2)) return fail(LB_EINVAL, "s_q must lie in (0, 2)");
+    if (!(p->tau_rho > 0.5) || !(p->tau_j > 0.5)) return fail(LB_EINVAL, "tau_rho and tau_j must exceed 1/2");
+    if (!std::isfinite(p->g)) return fail(LB_EINVAL, "g");
+    const int *k = nullptr;
+    int kinds[4];
+    for (int s = 0; s < 4; ++s) {
+        kinds[s] = p->side[s].kind;
+        if (kinds[s] < 0 || kinds[s] > 4) return fail(LB_EINVAL, "side kind");
+    }
+    (void)k;
+    if (side_bounded(kinds[0]) != side_bounded(kinds[1]) || side_bounded(kinds[2]) != side_bounded(kinds[3]))
+        return fail(LB_EINVAL, "both sides of an axis must be periodic or both bounded");
+    for (int s = 0; s < 4; ++s) {
+        if (kinds[s] == LB_BC_INLET && s != 0) return fail(LB_EINVAL, "inlet only at x-");
+        if (kinds[s] == LB_BC_OUTLET && s != 1) return fail(LB_EINVAL, "outlet only at x+");
+    }
+    const bool io = kinds[0] == LB_BC_INLET || kinds[1] == LB_BC_OUTLET || kinds[1] == LB_BC_INLET ||
+                    kinds[0] == LB_BC_OUTLET;
+    if (io && side_bounded(kinds[2])) return fail(LB_EINVAL, "inlet/outlet need a periodic y axis");
+    if ((side_bounded(kinds[0]) && p->nx < 3) || (side_bounded(kinds[2]) && p->ny < 3))
+        return fail(LB_EINVAL, "a bounded axis needs at least 3 nodes");
+    if (((kinds[0] == LB_BC_ADIABATIC || kinds[1] == LB_BC_ADIABATIC) && p->nx < 4) ||
+        ((kinds[2] == LB_BC_ADIABATIC || kinds[3] == LB_BC_ADIABATIC) && p->ny < 4))
+        return fail(LB_EINVAL, "an axis with an adiabatic wall needs at least 4 nodes");
+    const double cs = 1.0 / std::sqrt(3.0);
+    for (int s = 0; s < 4; ++s) {
+        const lb_side &sd = p->side[s];
+        if (kinds[s] == LB_BC_WALL || kinds[s] == LB_BC_ADIABATIC) {
+            if (!(std::hypot(sd.ux, sd.uy) < cs)) return fail(LB_EINVAL, "wall speed must stay below c_s");
+            if (kinds[s] == LB_BC_WALL && !(sd.T > 0)) return fail(LB_EINVAL, "wall temperature must be positive");
+        }
+        if (kinds[s] == LB_BC_INLET && (!(sd.period > 0) || !std::isfinite(sd.amp)))
+            return fail(LB_EINVAL, "inlet needs period > 0 and a finite amplitude");
+    }
+    return LB_OK;
+}
+
+}  // namespace
+
+struct lb_handle {
+    lb_params p;
+    Layout L;
+    KArgs a;
+    char *base;
+    char *pops[2];
+    float *snap;
+    double *partials, *red;
+    int cur;
+    long n;
+    int have_snap;
+    hipStream_t stream;
+    int strip_user;
+    int bc;
+    int red_blocks;
+    double E0;
+};
+
+namespace {
+
+void set_strip(lb_handle *h) {
+    KArgs &a = h->a;
+    a.tiles_x = (a.nx + kTile - 1) / kTile;
+    int R = h->strip_user;
+    if (R <= 0) {
+        // enough wavefronts to fill 256 CUs several times over, long strips otherwise
+        R = 64;
+        while (R > 4 && (long long)a.tiles_x * ((a.ny + R - 1) / R) < 16384) R >>= 1;
+    }
+    a.strip_rows = R;
+    a.n_strips = (a.ny + R - 1) / R;
+}
+
+KArgs make_args(const lb_params *p, const Layout &L, double &E0out) {
+    KArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.nx = p->nx;
+    a.ny = p->ny;
+    a.pitch = L.pitch;
+    a.per_x = !side_bounded(p->side[0].kind);
+    a.per_y = !side_bounded(p->side[2].kind);
+    a.plane_bytes = (long long)L.plane_bytes;
+    a.total = p->energy == LB_ENERGY_TOTAL;
+    a.heat = a.total && p->heating;
+    a.coupled = p->coupled != 0;
+    a.corr = p->correction && p->coupled;
+    a.bgk = p->collision == LB_COLLIDE_BGK;
+    a.visc = p->visc;
+    a.rho_press = p->rho_extrap == LB_RHO_PRESSURE;
+    a.has_force = p->g != 0.0;
+    const double E0 = 0.5 * p->b * p->R * p->T0;
+    E0out = E0;
+    a.rho0 = (float)p->rho0;
+    a.E0 = (float)E0;
+    a.inv_E0 = (float)(1.0 / E0);
+    a.g = (float)p->g;
+    a.half_g = (float)(0.5 * p->g);
+    a.Pr = (float)p->Pr;
+    if (p->visc == LB_VISC_CONST_TAU) {
+        const double tau = p->tau_f, snu = 1.0 / tau;
+        const double tau_h = (tau - 0.5) / p->Pr;
+        const double wh = 2.0 / (2.0 * tau_h + 1.0);
+        a.s_nu = (float)snu;
+        a.omega_h = (float)wh;
+        a.kcoup = (float)((1.0 - 0.5 * wh) * (p->Pr - 1.0) / tau);
+        a.s_e = (float)(p->s_e > 0 ? p->s_e : snu);
+        a.s_z = (float)(p->s_zeta > 0 ? p->s_zeta : snu);
+    } else {
+        a.s_e = (float)p->s_e;
+        a.s_z = (float)p->s_zeta;
+    }
+    a.tie_e = !(p->s_e > 0);
+    a.tie_z = !(p->s_zeta > 0);
+    a.s_q = (float)p->s_q;
+    a.s_rho = (float)(1.0 / p->tau_rho);
+    a.s_j = (float)(1.0 / p->tau_j);
+    a.mu3 = (float)(3.0 * p->mu_ref);
+    a.cT = (float)(p->T0 / p->T_ref);
+    a.visc_n = (float)p->visc_n;
+    a.sT = (float)(p->suth_S / p->T_ref);
+    for (int s = 0; s < 4; ++s) {
+        a.side_kind[s] = p->side[s].kind;
+        a.side_ux[s] = (float)p->side[s].ux;
+        a.side_uy[s] = (float)p->side[s].uy;
+        a.side_dth[s] = (float)(p->side[s].T / p->T0 - 1.0);
+    }
+    return a;
+}
+
+// inlet values at time step n (Eq. 53, 54), in double on the host
+void set_inlet(lb_handle *h, long n) {
+    const lb_params &p = h->p;
+    if (p.side[0].kind != LB_BC_INLET) return;
+    const double gamma = (p.b + 2.0) / p.b;
+    const double cs = std::sqrt(gamma * p.R * p.T0);
+    const double P = p.side[0].period;
+    const double ph = std::fmod((double)n, P) / P;
+    const double s = std::sin(2.0 * M_PI * ph);
+    const double U0 = p.side[0].amp;
+    h->a.in_ux = (float)(U0 * s);
+    h->a.in_drho = (float)(p.rho0 * U0 * s / cs);
+    h->a.in_dth = (float)((gamma - 1.0) * U0 * s / cs);
+}
+
+template <int ST, bool BC>
+void launch_step(lb_handle *h) {
+    const KArgs &a = h->a;
+    const long long waves = (long long)a.tiles_x * a.n_strips;
+    const int blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
+    hipLaunchKernelGGL((k_step<ST, BC>), dim3(blocks), dim3(kBlock), 0, h->stream, a, h->pops[h->cur],
+                       h->pops[1 - h->cur]);
+}
+
+typedef void (*step_fn)(lb_handle *);
+step_fn pick_step(int st, int bc) {
+    static const step_fn tbl[3][2] = {
+        {launch_step<LB_STORE_F32, false>, launch_step<LB_STORE_F32, true>},
+        {launch_step<LB_STORE_F16, false>, launch_step<LB_STORE_F16, true>},
+        {launch_step<LB_STORE_BF16, false>, launch_step<LB_STORE_BF16, true>},
+    };
+    return tbl[st][bc];
+}
+
+template <int ST, bool BC>
+void launch_macros(lb_handle *h, float *o0, float *o1, float *o2, float *o3, int opitch, int full) {
+    set_inlet(h, h->n);
+    const int n = h->a.nx * h->a.ny;
+    hipLaunchKernelGGL((k_macros<ST, BC>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, h->stream, h->a,
+                       h->pops[h->cur], o0, o1, o2, o3, opitch, full, (float)h->p.T0);
+}
+
+template <int ST, bool BC>
+void launch_pops(lb_handle *h, float *out, long long oplane, int q0, int nq) {
+    set_inlet(h, h->n);
+    const int n = h->a.nx * h->a.ny;
+    hipLaunchKernelGGL((k_pops<ST, BC>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, h->stream, h->a,
+                       h->pops[h->cur], out, oplane, q0, nq);
+}
+
+template <int ST, bool BC>
+void launch_diag(lb_handle *h, int use_snap, int write_snap) {
+    set_inlet(h, h->n);
+    hipLaunchKernelGGL((k_diag<ST, BC>), dim3(h->red_blocks), dim3(kBlock), 0, h->stream, h->a, h->pops[h->cur],
+                       h->snap, use_snap, write_snap, h->partials);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, h->stream, h->partials, h->red_blocks, h->red);
+}
+
+template <int ST>
+void launch_init(lb_handle *h, const float *fields, long long fplane) {
+    const int n = h->a.nx * h->a.ny;
+    hipLaunchKernelGGL((k_init<ST>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, h->stream, h->a, fields,
+                       fplane, h->pops[h->cur]);
+}
+
+#define DISPATCH(h, FN, ...)                                                                     \
+    do {                                                                                         \
+        const int st_ = (h)->p.storage, bc_ = (h)->bc;                                           \
+        if (st_ == LB_STORE_F32) {                                                               \
+            if (bc_) FN<LB_STORE_F32, true>(__VA_ARGS__); else FN<LB_STORE_F32, false>(__VA_ARGS__); \
+        } else if (st_ == LB_STORE_F16) {                                                        \
+            if (bc_) FN<LB_STORE_F16, true>(__VA_ARGS__); else FN<LB_STORE_F16, false>(__VA_ARGS__); \
+        } else {                                                                                 \
+            if (bc_) FN<LB_STORE_BF16, true>(__VA_ARGS__); else FN<LB_STORE_BF16, false>(__VA_ARGS__); \
+        }                                                                                        \
+    } while (0)
+
+lb_status run_diag(lb_handle *h, int use_snap, int write_snap, double out[kNred]) {
+    DISPATCH(h, launch_diag, h, use_snap, write_snap);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(out, h->red, kNred * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lb_status lb_validate(const lb_params *p) { return validate(p); }
+
+size_t lb_state_bytes(const lb_params *p) {
+    if (validate(p) != LB_OK) return 0;
+    return layout_of(p).total;
+}
+
+lb_status lb_create(const lb_params *p, void *dev_state, size_t bytes, void *hip_stream, lb_handle **out) {
+    if (!out) return fail(LB_EINVAL, "null output handle");
+    *out = nullptr;
+    lb_status s = validate(p);
+    if (s != LB_OK) return s;
+    const Layout L = layout_of(p);
+    if (!dev_state) return fail(LB_EINVAL, "null device buffer");
+    if (((uintptr_t)dev_state & 255) != 0) return fail(LB_EINVAL, "device buffer must be 256-byte aligned");
+    if (bytes < L.total) return fail(LB_ENOMEM, "device buffer smaller than lb_state_bytes()");
+    lb_handle *h = new lb_handle();
+    h->p = *p;
+    h->L = L;
+    h->a = make_args(p, L, h->E0);
+    h->base = (char *)dev_state;
+    h->pops[0] = h->base;
+    h->pops[1] = h->base + L.pops_bytes;
+    h->snap = (float *)(h->base + L.snap_off);
+    h->partials = (double *)(h->base + L.part_off);
+    h->red = (double *)(h->base + L.red_off);
+    h->cur = 0;
+    h->n = 0;
+    h->have_snap = 0;
+    h->stream = (hipStream_t)hip_stream;
+    h->strip_user = 0;
+    h->bc = !(h->a.per_x && h->a.per_y);
+    const long long nodes = (long long)p->nx * p->ny;
+    h->red_blocks = (int)std::min<long long>(kRedBlocks, (nodes + kBlock - 1) / kBlock);
+    set_strip(h);
+    *out = h;
+    return LB_OK;
+}
+
+void lb_destroy(lb_handle *h) { delete h; }
+
+const char *lb_last_error(void) { return g_err.c_str(); }
+
+long lb_time(const lb_handle *h) { return h ? h->n : -1; }
+
+void *lb_stream(const lb_handle *h) { return h ? (void *)h->stream : nullptr; }
+
+lb_status lb_set_strip_rows(lb_handle *h, int rows) {
+    if (!h) return fail(LB_EINVAL, "null handle");
+    if (rows < 0 || rows > 256 || (rows & (rows - 1)) != 0) return fail(LB_EINVAL, "strip rows: 0 or a power of two <= 256");
+    h->strip_user = rows;
+    set_strip(h);
+    return LB_OK;
+}
+
+int lb_strip_rows(const lb_handle *h) { return h ? h->a.strip_rows : -1; }
+
+lb_status lb_init(lb_handle *h, const double *rho, const double *ux, const double *uy, const double *T) {
+    if (!h) return fail(LB_EINVAL, "null handle");
+    const lb_params &p = h->p;
+    const int pitch = h->L.pitch;
+    const size_t fplane = (size_t)pitch * p.ny;
+    std::vector<float> host(4 * fplane, 0.f);
+    for (int y = 0; y < p.ny; ++y)
+        for (int x = 0; x < p.nx; ++x) {
+            const size_t i = (size_t)y * p.nx + x, k = (size_t)y * pitch + x;
+            host[k] = (float)(rho ? rho[i] - p.rho0 : 0.0);
+            host[fplane + k] = (float)(ux ? ux[i] : 0.0);
+            host[2 * fplane + k] = (float)(uy ? uy[i] : 0.0);
+            host[3 * fplane + k] = (float)(T ? T[i] / p.T0 - 1.0 : 0.0);
+        }
+    h->cur = 0;
+    h->n = 0;
+    h->have_snap = 0;
+    float *staging = (float *)h->pops[1];
+    HIPCHK(hipMemcpyAsync(staging, host.data(), host.size() * sizeof(float), hipMemcpyHostToDevice, h->stream));
+    switch (p.storage) {
+    case LB_STORE_F32: launch_init<LB_STORE_F32>(h, staging, (long long)fplane); break;
+    case LB_STORE_F16: launch_init<LB_STORE_F16>(h, staging, (long long)fplane); break;
+    default: launch_init<LB_STORE_BF16>(h, staging, (long long)fplane); break;
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+lb_status lb_step(lb_handle *h, long n) {
+    if (!h) return fail(LB_EINVAL, "null handle");
+    if (n < 0) return fail(LB_EINVAL, "negative step count");
+    const step_fn fn = pick_step(h->p.storage, h->bc);
+    for (long s = 0; s < n; ++s) {
+        set_inlet(h, h->n);
+        fn(h);
+        h->cur ^= 1;
+        h->n += 1;
+    }
+    HIPCHK(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status lb_macros(lb_handle *h, double *rho, double *ux, double *uy, double *T) {
+    if (!h) return fail(LB_EINVAL, "null handle");
+    const lb_params &p = h->p;
+    const int pitch = h->L.pitch;
+    const size_t fplane = (size_t)pitch * p.ny;
+    float *st = (float *)h->pops[1 - h->cur];
+    DISPATCH(h, launch_macros, h, st, st + fplane, st + 2 * fplane, st + 3 * fplane, pitch, 0);
+    HIPCHK(hipGetLastError());
+    std::vector<float> host(4 * fplane);
+    HIPCHK(hipMemcpyAsync(host.data(), st, host.size() * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int y = 0; y < p.ny; ++y)
+        for (int x = 0; x < p.nx; ++x) {
+            const size_t i = (size_t)y * p.nx + x, k = (size_t)y * pitch + x;
+            if (rho) rho[i] = p.rho0 + (double)host[k];
+            if (ux) ux[i] = host[fplane + k];
+            if (uy) uy[i] = host[2 * fplane + k];
+            if (T) T[i] = p.T0 * (1.0 + (double)host[3 * fplane + k]);
+        }
+    return LB_OK;
+}
+
+lb_status lb_macros_device(lb_handle *h, float *rho, float *ux, float *uy, float *T) {
+    if (!h) return fail(LB_EINVAL, "null handle");
+    DISPATCH(h, launch_macros, h, rho, ux, uy, T, h->p.nx, 1);
+    HIPCHK(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status lb_populations(lb_handle *h, double *out) {
+    if (!h || !out) return fail(LB_EINVAL, "null argument");
+    const lb_params &p = h->p;
+    const int pitch = h->L.pitch;
+    const size_t fplane = (size_t)pitch * p.ny;
+    float *st = (float *)h->pops[1 - h->cur];
+    const int per_pass = (int)std::min<size_t>(18, h->L.pops_bytes / (fplane * sizeof(float)));
+    // rest equilibria (rho0, 0, T0) in double
+    const double w[9] = {4. / 9, 1. / 9, 1. / 9, 1. / 9, 1. / 9, 1. / 36, 1. / 36, 1. / 36, 1. / 36};
+    const double e2[9] = {0, 1, 1, 1, 1, 2, 2, 2, 2};
+    double rest[18];
+    for (int q = 0; q < 9; ++q) {
+        rest[q] = w[q] * p.rho0;
+        rest[9 + q] = (p.energy == LB_ENERGY_TOTAL)
+                          ? w[q] * (p.rho0 * h->E0 + 0.5 * p.rho0 * p.R * p.T0 * (3.0 * e2[q] - 2.0))
+                          : w[q] * p.rho0 * h->E0;
+    }
+    std::vector<float> host((size_t)per_pass * fplane);
+    for (int q0 = 0; q0 < 18; q0 += per_pass) {
+        const int nq = std::min(per_pass, 18 - q0);
+        DISPATCH(h, launch_pops, h, st, (long long)fplane, q0, nq);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(host.data(), st, (size_t)nq * fplane * sizeof(float), hipMemcpyDeviceToHost, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+        for (int j = 0; j < nq; ++j)
+            for (int y = 0; y < p.ny; ++y)
+                for (int x = 0; x < p.nx; ++x)
+                    out[((size_t)(q0 + j) * p.ny + y) * p.nx + x] =
+                        rest[q0 + j] + (double)host[(size_t)j * fplane + (size_t)y * pitch + x];
+    }
+    return LB_OK;
+}
+
+lb_status lb_diag(lb_handle *h, double out[6]) {
+    if (!h || !out) return fail(LB_EINVAL, "null argument");
+    double r[kNred];
+    lb_status s = run_diag(h, 0, 0, r);
+    if (s != LB_OK) return s;
+    const double N = (double)h->p.nx * h->p.ny;
+    out[0] = N * h->p.rho0 + r[0];
+    out[1] = N * h->p.rho0 * h->E0 + r[1];
+    out[2] = r[2];
+    out[3] = r[3];
+    out[4] = r[4];
+    out[5] = (double)h->n;
+    if (r[4] > 0) return fail(LB_EUNSTABLE, "non-finite or non-positive moments on some nodes");
+    return LB_OK;
+}
+
+lb_status lb_residual(lb_handle *h, int update, double *res) {
+    if (!h || !res) return fail(LB_EINVAL, "null argument");
+    double r[kNred];
+    lb_status s = run_diag(h, h->have_snap, update ? 1 : 0, r);
+    if (s != LB_OK) return s;
+    *res = h->have_snap ? std::sqrt(r[5]) / std::sqrt(r[6]) : INFINITY;
+    if (update) h->have_snap = 1;
+    if (r[4] > 0) return fail(LB_EUNSTABLE, "non-finite or non-positive moments on some nodes");
+    return LB_OK;
+}
+
+size_t lb_checkpoint_bytes(const lb_handle *h) {
+    if (!h) return 0;
+    return 64 + h->L.pops_bytes + h->L.snap_bytes;
+}
+
+lb_status lb_save(lb_handle *h, void *host_buf) {
+    if (!h || !host_buf) return fail(LB_EINVAL, "null argument");
+    char *b = (char *)host_buf;
+    std::memset(b, 0, 64);
+    const long long hdr[6] = {0x4C42444446ll, (long long)h->p.nx, (long long)h->p.ny, (long long)h->p.storage,
+                              (long long)h->n, (long long)h->have_snap};
+    std::memcpy(b, hdr, sizeof(hdr));
+    HIPCHK(hipMemcpyAsync(b + 64, h->pops[h->cur], h->L.pops_bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(b + 64 + h->L.pops_bytes, h->snap, h->L.snap_bytes, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    return LB_OK;
+}
+
+lb_status lb_load(lb_handle *h, const void *host_buf) {
+    if (!h || !host_buf) return fail(LB_EINVAL, "null argument");
+    const char *b = (const char *)host_buf;
+    long long hdr[6];
+    std::memcpy(hdr, b, sizeof(hdr));
+    if (hdr[0] != 0x4C42444446ll || hdr[1] != h->p.nx || hdr[2] != h->p.ny || hdr[3] != h->p.storage)
+        return fail(LB_EINVAL, "checkpoint does not match this grid");
+    HIPCHK(hipMemcpyAsync(h->pops[0], b + 64, h->L.pops_bytes, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->snap, b + 64 + h->L.pops_bytes, h->L.snap_bytes, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    h->cur = 0;
+    h->n = (long)hdr[4];
+    h->have_snap = (int)hdr[5];
+    return LB_OK;
+}
+
+}  // extern "C"

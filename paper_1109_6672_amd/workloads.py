@@ -85,13 +85,17 @@ def gaussian(seed: int, count: int) -> np.ndarray:
     they yield r cos(2 pi u2) and r sin(2 pi u2) with r = sqrt(-2 ln u1).
     """
     npairs = (count + 1) // 2
-    z = splitmix64(seed, 2 * npairs)
-    u1 = ((z[0::2] >> np.uint64(11)).astype(np.float64) + 1.0) * (2.0 ** -53)
-    u2 = (z[1::2] >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
-    r = np.sqrt(-2.0 * np.log(u1))
     out = np.empty(2 * npairs, dtype=np.float64)
-    out[0::2] = r * np.cos(2.0 * math.pi * u2)
-    out[1::2] = r * np.sin(2.0 * math.pi * u2)
+    chunk = 1 << 22  # pairs per chunk, bounds the temporaries
+    for p0 in range(0, npairs, chunk):
+        n = min(chunk, npairs - p0)
+        z = splitmix64(seed, 2 * n, start=2 * p0)
+        u1 = ((z[0::2] >> np.uint64(11)).astype(np.float64) + 1.0) * (2.0 ** -53)
+        u2 = (z[1::2] >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+        r = np.sqrt(-2.0 * np.log(u1))
+        ang = (2.0 * math.pi) * u2
+        out[2 * p0:2 * (p0 + n):2] = r * np.cos(ang)
+        out[2 * p0 + 1:2 * (p0 + n):2] = r * np.sin(ang)
     return out[:count]
 
 
@@ -225,3 +229,17 @@ def noisy_temperature_fields(p: dict, amp: float = 1e-6, k: int = 2):
     rho, ux, uy, _ = rest_fields(p)
     T = p["T0"] * (1.0 + amp * (2.0 * u - 1.0))
     return rho, ux, uy, T
+
+
+def conduction_fields(p: dict, amp: float = 1e-6, k: int = 3):
+    """Pure-conduction start of the cavity: T linear between the x walls,
+    uniform pressure (rho = rho0 T0 / T), fluid at rest, plus seeded uniform
+    noise T0 U(-1, 1) amp on T (the paper states no initial condition)."""
+    ny, nx = p["ny"], p["nx"]
+    Th, Tc = p["sides"][0]["T"], p["sides"][1]["T"]
+    x = np.arange(nx) / (nx - 1)
+    T = np.broadcast_to(Th + (Tc - Th) * x, (ny, nx)).copy()
+    u = uniform01(SEED_BASE + k, nx * ny).reshape(ny, nx)
+    T[:, 1:-1] += p["T0"] * amp * (2.0 * u[:, 1:-1] - 1.0)
+    rho = p["rho0"] * p["T0"] / T
+    return rho, np.zeros((ny, nx)), np.zeros((ny, nx)), T

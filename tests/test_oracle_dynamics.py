@@ -260,3 +260,31 @@ def test_cavity_walls_and_corners():
     np.testing.assert_allclose(T[-1, 1:-1], (4 * T[-2, 1:-1] - T[-3, 1:-1]) / 3, rtol=0, atol=1e-15)
     # pressure extrapolation: rho_b T_b = rho_f T_f at Dirichlet walls
     np.testing.assert_allclose(rho[1:-1, 0] * T[1:-1, 0], rho[1:-1, 1] * T[1:-1, 1], rtol=1e-15)
+
+
+def test_applied_correction_meets_eq28_on_the_grid():
+    """One step with and without the correction term from the same state: the
+    difference of the post-collision f is (1 - s/2) C with C of Eq. 49, whose
+    second moments are the Eq. 50 differences of Q = rho u (1 - theta) (Eq. 28)
+    and whose mass, momentum and off-diagonal moments vanish (Eq. 26, 28)."""
+    ex, ey, _ = O.lattice()
+    p = W.periodic(16, 12, tau_f=0.8)
+    p.update(heating=False, s_e=0.0, s_zeta=0.0)
+    f = W.gaussian_fields(p, sigma=2e-2)
+    on = _run(dict(p, correction=True), f)
+    rho, ux, uy, T = on.macros()
+    on.step(1)
+    off = _run(dict(p, correction=False), f, 1)
+    diff = on.pops()[:9] - off.pops()[:9]
+    # undo the streaming: post-collision value of node x travelled to x + e_a
+    post = np.stack([np.roll(np.roll(diff[a], -ey[a], 0), -ex[a], 1) for a in range(9)])
+    Qx, Qy = rho * ux * (1 - T), rho * uy * (1 - T)
+    dQx = 0.5 * (np.roll(Qx, -1, 1) - np.roll(Qx, 1, 1))
+    dQy = 0.5 * (np.roll(Qy, -1, 0) - np.roll(Qy, 1, 0))
+    k = 1 - 0.5 / 0.8
+    mom = lambda w: np.tensordot(w, post, axes=(0, 0))
+    np.testing.assert_allclose(mom(ex * ex * 1.0), k * dQx, atol=1e-15)
+    np.testing.assert_allclose(mom(ey * ey * 1.0), k * dQy, atol=1e-15)
+    for w in (np.ones(9), ex * 1.0, ey * 1.0, ex * ey * 1.0):
+        assert np.abs(mom(w)).max() < 1e-15
+    assert np.abs(dQx).max() > 1e-6
