@@ -40,12 +40,12 @@
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kTile = 62;  // owned columns per wavefront
+constexpr int kTile = 64;  // owned columns per wavefront (aligned)
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
 constexpr int kRedBlocks = 1024;
 constexpr int kNred = 8;
-constexpr int kPlanePad = 320;  // elements appended to each plane (64-aligned)
+constexpr int kPlanePadBytes = 4096;  // appended to each plane: spreads the 18 streams over HBM channels
 
 enum : int { K_INTERIOR = 0, K_DIRICHLET = 1, K_ADIABATIC = 2, K_INLET = 3, K_OUTLET = 4 };
 
@@ -65,24 +65,75 @@ struct KArgs {
     // sides x-, x+, y-, y+
     int side_kind[4];
     float side_ux[4], side_uy[4], side_dth[4];
-    // inlet state at the launch's time step
+    // inlet state and time step of the launch
     float in_drho, in_ux, in_dth;
+    unsigned step;
 };
 
 // Reciprocal: hardware estimate plus one Newton step, so that rho * (j / rho)
 // reproduces j without the systematic bias of the raw estimate.
+// Model switches: Dyn reads them from the kernel arguments; Head fixes the
+// ones of the main throughput configuration (total energy with the heating
+// term, theta-coupled equilibria, correction term, no body force, MRT,
+// constant tau_f) at compile time so that no dead branch is evaluated.
+struct Dyn {
+    static constexpr bool fixed = false, total = false, heat = false, coupled = false, corr = false,
+                          force = false, bgk = false, ctau = false;
+};
+struct Head {
+    static constexpr bool fixed = true, total = true, heat = true, coupled = true, corr = true, force = false,
+                          bgk = false, ctau = true;
+};
+#define F_TOTAL (F::fixed ? F::total : (bool)a.total)
+#define F_HEAT (F::fixed ? F::heat : (bool)a.heat)
+#define F_COUPLED (F::fixed ? F::coupled : (bool)a.coupled)
+#define F_CORR (F::fixed ? F::corr : (bool)a.corr)
+#define F_FORCE (F::fixed ? F::force : (bool)a.has_force)
+#define F_BGK (F::fixed ? F::bgk : (bool)a.bgk)
+#define F_CTAU (F::fixed ? F::ctau : (a.visc == LB_VISC_CONST_TAU))
+
 __device__ __forceinline__ float frcp(float x) {
     const float r = __builtin_amdgcn_rcpf(x);
     return fmaf(r, fmaf(-x, r, 1.f), r);
 }
 
 // ------------------------------------------------------------------ storage
-template <int ST> struct Codec;
+// A population buffer is addressed through two raw buffer resources, one for
+// the 9 f-planes and one for the 9 h-planes (each spans less than 4 GiB): the
+// per-lane byte offset of the node goes in a VGPR, the plane offset in an
+// SGPR, so no load or store spends vector instructions on 64-bit addresses.
+typedef __amdgpu_buffer_rsrc_t Rsrc;
+// cache policy of the population stores: non-temporal (each value is written
+// once per step and read back only in the next step).  Loads stay cached:
+// neighbouring lanes, tiles and the halo gather share their cache lines.
+constexpr int kNT = 2;
+
+struct Planes {
+    Rsrc f, h;
+    unsigned pb;  // bytes per plane
+};
+
+__device__ __forceinline__ Planes planes(const char *base, long long pb) {
+    Planes P;
+    const unsigned half = (unsigned)(9 * pb);
+    P.f = __builtin_amdgcn_make_buffer_rsrc((void *)base, (short)0, (int)half, 0x00020000);
+    P.h = __builtin_amdgcn_make_buffer_rsrc((void *)(base + 9 * pb), (short)0, (int)half, 0x00020000);
+    P.pb = (unsigned)pb;
+    return P;
+}
+
 // q is the plane (0..17); after unrolling it is a compile-time constant.
+template <int ST> struct Codec;
 template <> struct Codec<LB_STORE_F32> {
-    typedef float T;
-    static __device__ __forceinline__ float ld(const T *p, unsigned i, int) { return p[i]; }
-    static __device__ __forceinline__ void st(T *p, unsigned i, float v, int) { p[i] = v; }
+    static constexpr unsigned bytes = 4;
+    static __device__ __forceinline__ float ld(const Planes &P, unsigned vo, int q) {
+        const Rsrc r = q < 9 ? P.f : P.h;
+        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, (q % 9) * P.pb, 0));
+    }
+    static __device__ __forceinline__ void st(const Planes &P, unsigned vo, float v, int q, unsigned) {
+        const Rsrc r = q < 9 ? P.f : P.h;
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, (q % 9) * P.pb, kNT);
+    }
 };
 // FP16 keeps deviation * 2^(8 + k_a), k_a = 1, 3, 5 for the rest, axis and
 // diagonal velocities (about 1 / w_a): every plane then spans the same
@@ -93,29 +144,39 @@ __device__ __forceinline__ float f16_scale(int q) {
     return a == 0 ? 512.f : (a < 5 ? 2048.f : 8192.f);
 }
 template <> struct Codec<LB_STORE_F16> {
-    typedef _Float16 T;
-    static __device__ __forceinline__ float ld(const T *p, unsigned i, int q) { return (float)p[i] * (1.f / f16_scale(q)); }
-    static __device__ __forceinline__ void st(T *p, unsigned i, float v, int q) { p[i] = (_Float16)(v * f16_scale(q)); }
-};
-template <> struct Codec<LB_STORE_BF16> {
-    typedef unsigned short T;
-    static __device__ __forceinline__ float ld(const T *p, unsigned i, int) { return __uint_as_float(((unsigned)p[i]) << 16); }
-    static __device__ __forceinline__ void st(T *p, unsigned i, float v, int) {
-        // round to nearest even
-        unsigned u = __float_as_uint(v);
-        u += 0x7FFFu + ((u >> 16) & 1u);
-        p[i] = (unsigned short)(u >> 16);
+    static constexpr unsigned bytes = 2;
+    static __device__ __forceinline__ float ld(const Planes &P, unsigned vo, int q) {
+        const Rsrc r = q < 9 ? P.f : P.h;
+        const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, (q % 9) * P.pb, 0);
+        return (float)__builtin_bit_cast(_Float16, b) * (1.f / f16_scale(q));
+    }
+    // rb: random bits; the 13 float mantissa bits below the FP16 mantissa are
+    // rounded stochastically (add, then truncate), which leaves no systematic
+    // rounding bias in steady flows.  rb = 0 gives round-toward-zero of those
+    // bits followed by an exact conversion.
+    static __device__ __forceinline__ void st(const Planes &P, unsigned vo, float v, int q, unsigned rb) {
+        const Rsrc r = q < 9 ? P.f : P.h;
+        unsigned u = __float_as_uint(v * f16_scale(q));
+        u = (u + (rb >> 19)) & ~0x1FFFu;
+        const _Float16 h = (_Float16)__uint_as_float(u);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, vo, (q % 9) * P.pb, kNT);
     }
 };
-
-template <int ST>
-__device__ __forceinline__ const typename Codec<ST>::T *cplane(const char *base, long long pb, int q) {
-    return reinterpret_cast<const typename Codec<ST>::T *>(base + (long long)q * pb);
-}
-template <int ST>
-__device__ __forceinline__ typename Codec<ST>::T *wplane(char *base, long long pb, int q) {
-    return reinterpret_cast<typename Codec<ST>::T *>(base + (long long)q * pb);
-}
+template <> struct Codec<LB_STORE_BF16> {
+    static constexpr unsigned bytes = 2;
+    static __device__ __forceinline__ float ld(const Planes &P, unsigned vo, int q) {
+        const Rsrc r = q < 9 ? P.f : P.h;
+        const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, (q % 9) * P.pb, 0);
+        return __uint_as_float(((unsigned)b) << 16);
+    }
+    // stochastic rounding of the 16 dropped mantissa bits (see the FP16 codec)
+    static __device__ __forceinline__ void st(const Planes &P, unsigned vo, float v, int q, unsigned rb) {
+        const Rsrc r = q < 9 ? P.f : P.h;
+        unsigned u = __float_as_uint(v);
+        u += rb >> 16;
+        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(u >> 16), r, vo, (q % 9) * P.pb, kNT);
+    }
+};
 
 // --------------------------------------------------------- node primitives
 // drho = rho - rho0, j = rho u (the momentum of Eq. 46 with the forcing note),
@@ -130,23 +191,26 @@ struct Mom {
 // value stored at (x, y) - e_a, with periodic wrap.  Sources of a bounded
 // axis are interior nodes, so their neighbours never leave the domain.
 template <int ST>
-__device__ __forceinline__ void gather(const KArgs &a, const char *__restrict__ src, int x, int y, float d[18]) {
+__device__ __forceinline__ void gather(const KArgs &a, const Planes &S, int x, int y, float d[18]) {
     int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
     xm += (xm < 0) ? a.nx : 0;
     xp -= (xp >= a.nx) ? a.nx : 0;
     ym += (ym < 0) ? a.ny : 0;
     yp -= (yp >= a.ny) ? a.ny : 0;
+    const unsigned eb = Codec<ST>::bytes;
     const unsigned rm = (unsigned)ym * a.pitch, rc = (unsigned)y * a.pitch, rp = (unsigned)yp * a.pitch;
-    const unsigned o[9] = {rc + x, rc + xm, rm + x, rc + xp, rp + x, rm + xm, rm + xp, rp + xp, rp + xm};
+    const unsigned o[9] = {(rc + x) * eb,  (rc + xm) * eb, (rm + x) * eb,  (rc + xp) * eb, (rp + x) * eb,
+                           (rm + xm) * eb, (rm + xp) * eb, (rp + xp) * eb, (rp + xm) * eb};
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        d[q] = Codec<ST>::ld(cplane<ST>(src, a.plane_bytes, q), o[q], q);
-        d[9 + q] = Codec<ST>::ld(cplane<ST>(src, a.plane_bytes, 9 + q), o[q], 9 + q);
+        d[q] = Codec<ST>::ld(S, o[q], q);
+        d[9 + q] = Codec<ST>::ld(S, o[q], 9 + q);
     }
 }
 
 // Eq. 46 with the forcing note (rho u = sum e f + a/2, a = (0, -rho g)) and
 // Eq. 37 / the internal-energy form, written for deviations from rest.
+template <class F>
 __device__ __forceinline__ Mom moments(const KArgs &a, const float d[18]) {
     Mom m;
     const float s1 = (d[1] + d[3]) + (d[2] + d[4]);
@@ -160,12 +224,12 @@ __device__ __forceinline__ Mom moments(const KArgs &a, const float d[18]) {
     m.rho = a.rho0 + m.drho;
     const float ir = frcp(m.rho);
     m.jx = jx;
-    m.jy = jy - a.half_g * m.rho;
+    m.jy = F_FORCE ? jy - a.half_g * m.rho : jy;
     m.ux = m.jx * ir;
     m.uy = m.jy * ir;
     const float sh = ((d[9] + d[10]) + (d[11] + d[12])) + ((d[13] + d[14]) + (d[15] + d[16])) + d[17];
     const float e = (sh - m.drho * a.E0) * ir;  // E - E0 (total) or (rho E_int - rho E0)/rho
-    m.dth = a.total ? (e - 0.5f * (m.ux * m.ux + m.uy * m.uy)) * a.inv_E0 : e * a.inv_E0;
+    m.dth = F_TOTAL ? (e - 0.5f * (m.ux * m.ux + m.uy * m.uy)) * a.inv_E0 : e * a.inv_E0;
     return m;
 }
 
@@ -174,9 +238,10 @@ __device__ __forceinline__ Mom moments(const KArgs &a, const float d[18]) {
 // j = rho u so that the first moment of f_eq is j itself:
 //   f_eq - f_rest = w [drho + c rho th - 1.5 j.u + (e.j)(B + 4.5 e.u)],
 //   c = -1, 1/2, 2 and B = 3, 3 - 1.5 th, 3 + 3 th for |e|^2 = 0, 1, 2.
+template <class F>
 __device__ __forceinline__ void equilibria(const KArgs &a, const Mom &m, float fe[9], float he[9]) {
     const float w0 = 4.f / 9.f, w1 = 1.f / 9.f, w2 = 1.f / 36.f;
-    const float th = a.coupled ? m.dth : 0.f;  // theta_eq - 1
+    const float th = F_COUPLED ? m.dth : 0.f;  // theta_eq - 1
     const float ux = m.ux, uy = m.uy, jx = m.jx, jy = m.jy, drho = m.drho, rho = m.rho;
     const float ju = jx * ux + jy * uy;
     const float base = drho - 1.5f * ju;
@@ -194,7 +259,7 @@ __device__ __forceinline__ void equilibria(const KArgs &a, const Mom &m, float f
     fe[6] = w2 * (A2 + j6 * (B2 + 4.5f * v6));
     fe[8] = w2 * (A2 - j6 * (B2 - 4.5f * v6));
     const float u2 = ux * ux + uy * uy;
-    if (a.total) {
+    if (F_TOTAL) {
         // h_eq - h_rest = w [rho0 (E - E0) + c (p theta - p0) + p (3 eu + 9 eu^2 - 3 u^2)] + E (f_eq - f_rest),
         // p (3 eu + 9 eu^2 - 3 u^2) = theta [(e.j)(1 + 3 e.u) - j.u] with p = rho theta / 3
         const float E = a.E0 * (1.f + m.dth) + 0.5f * u2;
@@ -229,9 +294,10 @@ struct Relax {
 // Per-node transport: tau_f = mu(T) / p + 1/2 (Sec. IV-C) for the viscosity
 // laws, tau_h = (tau_f - 1/2)/Pr, omega_h = 2/(2 tau_h + 1),
 // coupling factor (1 - omega_h/2)(Pr - 1)/tau_f (Eq. 47).
+template <class F>
 __device__ __forceinline__ Relax transport(const KArgs &a, float rho, float dth) {
     Relax t;
-    if (a.visc == LB_VISC_CONST_TAU) {
+    if (F_CTAU) {
         t.s_nu = a.s_nu;
         t.s_e = a.s_e;
         t.s_z = a.s_z;
@@ -304,18 +370,26 @@ __device__ __forceinline__ BInfo classify(const KArgs &a, int x, int y) {
     return b;
 }
 
-// State of node (x, y) at the current time after the boundary treatment:
-// deviations d[18], moments, kind.
+// The state of node (x, y) at the current time after the boundary treatment
+// comes in two parts so that the loads can be issued early: node_issue
+// gathers the populations of the node a boundary node extrapolates from (the
+// node itself otherwise), node_finish computes the moments and rebuilds the
+// populations of boundary nodes.  Returns the node kind.
 template <int ST, bool BC>
-__device__ __forceinline__ int node_state(const KArgs &a, const char *__restrict__ src, int x, int y, float d[18], Mom &m) {
+__device__ __forceinline__ void node_issue(const KArgs &a, const Planes &S, int x, int y, float d[18]) {
     if (!BC) {
-        gather<ST>(a, src, x, y, d);
-        m = moments(a, d);
-        return K_INTERIOR;
+        gather<ST>(a, S, x, y, d);
+        return;
     }
     const BInfo b = classify(a, x, y);
-    gather<ST>(a, src, b.fx, b.fy, d);
-    m = moments(a, d);
+    gather<ST>(a, S, b.fx, b.fy, d);
+}
+
+template <int ST, bool BC, class F>
+__device__ __forceinline__ int node_finish(const KArgs &a, const Planes &S, int x, int y, float d[18], Mom &m) {
+    m = moments<F>(a, d);
+    if (!BC) return K_INTERIOR;
+    const BInfo b = classify(a, x, y);
     if (b.kind == K_INTERIOR || b.kind == K_OUTLET) return b.kind;  // outlet: exact copy of the neighbour
     Mom mb;
     if (b.kind == K_INLET) {
@@ -327,10 +401,10 @@ __device__ __forceinline__ int node_state(const KArgs &a, const char *__restrict
         mb.jx = mb.rho * mb.ux;
         mb.jy = 0.f;
         float he[9];
-        equilibria(a, mb, d, he);
+        equilibria<F>(a, mb, d, he);
 #pragma unroll
         for (int q = 0; q < 9; ++q) d[9 + q] = he[q];
-        const Mom raw = moments(a, d);
+        const Mom raw = moments<F>(a, d);
         mb.sf = raw.sf;
         mb.sx = raw.sx;
         mb.sy = raw.sy;
@@ -344,8 +418,8 @@ __device__ __forceinline__ int node_state(const KArgs &a, const char *__restrict
     } else {
         // T_b = (4 T_1 - T_2) / 3 along the inward normal
         float d2[18];
-        gather<ST>(a, src, 2 * b.fx - x, 2 * b.fy - y, d2);
-        const Mom m2 = moments(a, d2);
+        gather<ST>(a, S, 2 * b.fx - x, 2 * b.fy - y, d2);
+        const Mom m2 = moments<F>(a, d2);
         mb.dth = (4.f * m.dth - m2.dth) * (1.f / 3.f);
     }
     // pressure extrapolation rho_b T_b = rho_f T_f, or rho_b = rho_f
@@ -354,14 +428,14 @@ __device__ __forceinline__ int node_state(const KArgs &a, const char *__restrict
     mb.jx = mb.rho * mb.ux;
     mb.jy = mb.rho * mb.uy;
     float fb[9], hb[9], ff[9], hf[9];
-    equilibria(a, mb, fb, hb);
-    equilibria(a, m, ff, hf);
+    equilibria<F>(a, mb, fb, hb);
+    equilibria<F>(a, m, ff, hf);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         d[q] += fb[q] - ff[q];
         d[9 + q] += hb[q] - hf[q];
     }
-    const Mom raw = moments(a, d);
+    const Mom raw = moments<F>(a, d);
     mb.sf = raw.sf;
     mb.sx = raw.sx;
     mb.sy = raw.sy;
@@ -369,12 +443,19 @@ __device__ __forceinline__ int node_state(const KArgs &a, const char *__restrict
     return b.kind;
 }
 
+template <int ST, bool BC>
+__device__ __forceinline__ int node_state(const KArgs &a, const Planes &S, int x, int y, float d[18], Mom &m) {
+    node_issue<ST, BC>(a, S, x, y, d);
+    return node_finish<ST, BC, Dyn>(a, S, x, y, d, m);
+}
+
 // Collision of one node (Eq. 44 or Eq. 34 for f^, Eq. 47 or Eq. 38 for h-),
 // deviations in d, results in o.
+template <class F>
 __device__ __forceinline__ void collide(const KArgs &a, const float d[18], const Mom &m, int kind, float phix,
                                         float phiy, float o[18]) {
     float fe[9], he[9];
-    equilibria(a, m, fe, he);
+    equilibria<F>(a, m, fe, he);
     if (kind == K_INLET) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -383,7 +464,7 @@ __device__ __forceinline__ void collide(const KArgs &a, const float d[18], const
         }
         return;
     }
-    const Relax t = transport(a, m.rho, m.dth);
+    const Relax t = transport<F>(a, m.rho, m.dth);
     const float ux = m.ux, uy = m.uy;
     const float ay = -m.rho * a.g;
     // velocity-space sources C = M^-1 (C^ + F^): Eq. 49 plus the forcing term
@@ -396,7 +477,7 @@ __device__ __forceinline__ void collide(const KArgs &a, const float d[18], const
         C[1] = C[3] = cx1 + cy;
         C[2] = C[4] = cx1 - cy;
         C[5] = C[6] = C[7] = C[8] = cx2;
-        if (a.has_force) {
+        if (F_FORCE) {
             const float f3 = -3.f * uy * ay;
             C[0] += w0 * f3;
             C[1] += w1 * f3;
@@ -412,8 +493,8 @@ __device__ __forceinline__ void collide(const KArgs &a, const float d[18], const
     {
         // BGK (Eq. 34) is the MRT scheme with every rate equal to 1/tau_f, so both
         // run through the same moment-space increments.
-        const float sr = a.bgk ? t.s_nu : a.s_rho, sj = a.bgk ? t.s_nu : a.s_j;
-        const float se = a.bgk ? t.s_nu : t.s_e, sz = a.bgk ? t.s_nu : t.s_z, sq = a.bgk ? t.s_nu : a.s_q;
+        const float sr = F_BGK ? t.s_nu : a.s_rho, sj = F_BGK ? t.s_nu : a.s_j;
+        const float se = F_BGK ? t.s_nu : t.s_e, sz = F_BGK ? t.s_nu : t.s_z, sq = F_BGK ? t.s_nu : a.s_q;
         // moments of the deviations, m = M f (Eq. B1); the conserved ones are
         // the raw sums, so that their increments vanish exactly on interior nodes
         const float s1 = (d[1] + d[3]) + (d[2] + d[4]);
@@ -427,7 +508,7 @@ __device__ __forceinline__ void collide(const KArgs &a, const float d[18], const
         const float m7 = (d[1] + d[3]) - (d[2] + d[4]);
         const float m8 = (d[5] + d[7]) - (d[6] + d[8]);
         // equilibria Eq. 41 minus M f_rest
-        const float thE = a.coupled ? m.dth : 0.f;
+        const float thE = F_COUPLED ? m.dth : 0.f;
         const float rho = m.rho;
         const float qq = 3.f * (m.jx * ux + m.jy * uy) + 2.f * rho * thE;
         const float e1 = -2.f * m.drho + qq, e2 = m.drho - qq;
@@ -467,7 +548,7 @@ __device__ __forceinline__ void collide(const KArgs &a, const float d[18], const
     const float wh = t.omega_h;
 #pragma unroll
     for (int q = 0; q < 9; ++q) o[9 + q] = d[9 + q] - wh * (d[9 + q] - he[q]);
-    if (a.heat) {
+    if (F_HEAT) {
         const float k = t.kcoup;
         const float v5 = ux + uy, v6 = uy - ux;
         const float z[9] = {0.f, ux, uy, -ux, -uy, v5, v6, -v5, -v6};
@@ -476,83 +557,150 @@ __device__ __forceinline__ void collide(const KArgs &a, const float d[18], const
     }
 }
 
+// Counter-based random bits for the stochastic rounding of the 16-bit codecs:
+// a 32-bit integer hash (two multiply-xorshift rounds) of the node's linear
+// index and the time step, spread over the 18 planes by odd multipliers.
+__device__ __forceinline__ unsigned hash32(unsigned x) {
+    x ^= x >> 16;
+    x *= 0x7feb352du;
+    x ^= x >> 15;
+    x *= 0x846ca68bu;
+    x ^= x >> 16;
+    return x;
+}
+__device__ __forceinline__ unsigned plane_bits(unsigned h, int q) { return h * (0x9E3779B1u + 2u * (unsigned)q); }
+
 __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
     const int xcd = b & 7, idx = b >> 3, per = nb >> 3, rem = nb & 7;
     return xcd * per + min(xcd, rem) + idx;
 }
 
-// Row state of the lane's column for row y of the marching strip (y may be
-// -1 or ny): deviations, moments, kind, and Q = rho u (1 - theta) (Eq. 48),
-// zero outside the domain of a bounded axis.
-template <int ST, bool BC>
-__device__ __forceinline__ int row_state(const KArgs &a, const char *__restrict__ src, int xw, bool xin, int y,
-                                         float d[18], Mom &m, float &Qx, float &Qy) {
-    int yw;
-    bool yin;
+// Rows of the marching strip: y may be -1 or ny.  A periodic axis wraps; a
+// bounded one clamps (those rows only feed Q, which is then zero, to
+// boundary nodes, whose correction term is zero anyway).
+__device__ __forceinline__ int row_wrap(const KArgs &a, int y, bool &yin) {
     if (a.per_y) {
-        yw = y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
         yin = true;
-    } else {
-        yin = (y >= 0) && (y < a.ny);
-        yw = min(max(y, 0), a.ny - 1);
+        return y < 0 ? y + a.ny : (y >= a.ny ? y - a.ny : y);
     }
-    const int kind = node_state<ST, BC>(a, src, xw, yw, d, m);
-    const float mq = (a.corr && xin && yin) ? -m.rho * m.dth : 0.f;
+    yin = (y >= 0) && (y < a.ny);
+    return min(max(y, 0), a.ny - 1);
+}
+
+template <int ST, bool BC>
+__device__ __forceinline__ void row_issue(const KArgs &a, const Planes &S, int xw, int y, float d[18]) {
+    bool yin;
+    const int yw = row_wrap(a, y, yin);
+    node_issue<ST, BC>(a, S, xw, yw, d);
+}
+
+// Moments, kind and Q = rho u (1 - theta) (Eq. 48) of the lane's node in row y.
+template <int ST, bool BC, class F>
+__device__ __forceinline__ int row_finish(const KArgs &a, const Planes &S, int xw, bool xin, int y, float d[18],
+                                          Mom &m, float &Qx, float &Qy) {
+    bool yin;
+    const int yw = row_wrap(a, y, yin);
+    const int kind = node_finish<ST, BC, F>(a, S, xw, yw, d, m);
+    const float mq = (F_CORR && xin && yin) ? -m.rho * m.dth : 0.f;
     Qx = mq * m.ux;
     Qy = mq * m.uy;
     return kind;
 }
 
+// Correction term from the Q of the neighbours (Eq. 50: central differences;
+// x-neighbours from the adjacent lanes, the two tile-edge neighbours from the
+// halo values qhl, qhr), collision, store of the owned lanes.
+template <int ST, bool BC, class F>
+__device__ __forceinline__ void collide_store(const KArgs &a, const Planes &D, const float d[18], const Mom &m,
+                                              int kind, int lane, float qxc, float qhl, float qhr, float qyp,
+                                              float qyn, bool owned, unsigned vo) {
+    float qxl = __shfl_up(qxc, 1), qxr = __shfl_down(qxc, 1);
+    qxl = lane == 0 ? qhl : qxl;
+    qxr = lane == kWave - 1 ? qhr : qxr;
+    const float dQx = 0.5f * (qxr - qxl), dQy = 0.5f * (qyn - qyp);
+    float phix = 3.f * (dQx + dQy), phiy = dQx - dQy;
+    if (BC && kind != K_INTERIOR) phix = phiy = 0.f;
+    float o[18];
+    collide<F>(a, d, m, kind, phix, phiy, o);
+    if (owned) {
+        const unsigned h = ST == LB_STORE_F32 ? 0u : hash32((vo / Codec<ST>::bytes) ^ (a.step * 0x9E3779B9u));
+#pragma unroll
+        for (int q = 0; q < 18; ++q) Codec<ST>::st(D, vo, o[q], q, plane_bits(h, q));
+    }
+}
+
+// x-component of Q at the two columns just outside the wavefront's tile for
+// row y: lane 0 computes column x0 - 1, lane 1 column x0 + 64 (the other lanes
+// repeat a valid node and are ignored); the values are broadcast to the wave.
+template <int ST, bool BC, class F>
+__device__ __forceinline__ void halo_q(const KArgs &a, const Planes &S, int hxw, bool hxin, int y, float &qhl,
+                                       float &qhr) {
+    float dh[18];
+    Mom mh;
+    float qx, qy;
+    row_issue<ST, BC>(a, S, hxw, y, dh);
+    row_finish<ST, BC, F>(a, S, hxw, hxin, y, dh, mh, qx, qy);
+    qhl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qx), 0));
+    qhr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qx), 1));
+}
+
+// lane's column x of a tile, wrapped (periodic) or clamped (bounded); xin
+// tells whether x lies inside the domain.
+__device__ __forceinline__ int col_wrap(const KArgs &a, int x, bool &xin) {
+    if (a.per_x) {
+        xin = true;
+        int xw = x % a.nx;
+        return xw + ((xw < 0) ? a.nx : 0);
+    }
+    xin = (x >= 0) && (x < a.nx);
+    return min(max(x, 0), a.nx - 1);
+}
+
 // ----------------------------------------------------------------- kernels
-template <int ST, bool BC>
+template <int ST, bool BC, class F>
 __global__ __launch_bounds__(kBlock) void k_step(const KArgs a, const char *__restrict__ src, char *__restrict__ dst) {
     const int lane = threadIdx.x & (kWave - 1);
     const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
     const int wv = blk * kWavesPerBlock + (threadIdx.x >> 6);
     if (wv >= a.tiles_x * a.n_strips) return;
     const int tx = wv % a.tiles_x, sy = wv / a.tiles_x;
-    const int gx = tx * kTile - 1 + lane;
-    int xw;
-    bool xin;
-    if (a.per_x) {
-        xw = gx % a.nx;
-        xw += (xw < 0) ? a.nx : 0;
-        xin = true;
-    } else {
-        xin = (gx >= 0) && (gx < a.nx);
-        xw = min(max(gx, 0), a.nx - 1);
-    }
-    const bool owned = (lane >= 1) && (lane <= kTile) && (gx < a.nx);
+    const int x0 = tx * kTile, gx = x0 + lane;
+    bool xin, hxin;
+    const int xw = col_wrap(a, gx, xin);
+    const int hxw = col_wrap(a, lane == 0 ? x0 - 1 : (lane == 1 ? x0 + kTile : gx), hxin);
+    const bool owned = gx < a.nx;
     const int y0 = sy * a.strip_rows;
     const int y1 = min(y0 + a.strip_rows, a.ny);
+    const Planes S = planes(src, a.plane_bytes), D = planes(dst, a.plane_bytes);
+    const unsigned eb = Codec<ST>::bytes, pitch_b = (unsigned)a.pitch * eb;
+    unsigned vo = ((unsigned)y0 * a.pitch + xw) * eb;
 
-    float dc[18], dn[18];
-    Mom mc, mn;
-    float qxp, qyp, qxc, qyc, qxn, qyn;
-    row_state<ST, BC>(a, src, xw, xin, y0 - 1, dc, mc, qxp, qyp);
-    int kc = row_state<ST, BC>(a, src, xw, xin, y0, dc, mc, qxc, qyc);
-    for (int y = y0; y < y1; ++y) {
-        const int kn = row_state<ST, BC>(a, src, xw, xin, y + 1, dn, mn, qxn, qyn);
-        // Eq. 50: central differences of Q, x-neighbours from the adjacent lanes
-        const float qxl = __shfl_up(qxc, 1), qxr = __shfl_down(qxc, 1);
-        const float dQx = 0.5f * (qxr - qxl), dQy = 0.5f * (qyn - qyp);
-        float phix = 3.f * (dQx + dQy), phiy = dQx - dQy;
-        if (BC && kc != K_INTERIOR) phix = phiy = 0.f;
-        float o[18];
-        collide(a, dc, mc, kc, phix, phiy, o);
-        if (owned) {
-            const unsigned idx = (unsigned)y * a.pitch + xw;
-#pragma unroll
-            for (int q = 0; q < 18; ++q) Codec<ST>::st(wplane<ST>(dst, a.plane_bytes, q), idx, o[q], q);
-        }
-        qxp = qxc;
-        qyp = qyc;
-        qxc = qxn;
-        qyc = qyn;
-#pragma unroll
-        for (int q = 0; q < 18; ++q) dc[q] = dn[q];
-        mc = mn;
-        kc = kn;
+    // two row states used alternately (the loop is unrolled by two)
+    float dA[18], dB[18];
+    Mom mA, mB;
+    float qyp, qxA, qyA, qxB, qyB, qhl, qhr;
+    row_issue<ST, BC>(a, S, xw, y0 - 1, dA);
+    row_finish<ST, BC, F>(a, S, xw, xin, y0 - 1, dA, mA, qxA, qyp);
+    row_issue<ST, BC>(a, S, xw, y0, dA);
+    int kA = row_finish<ST, BC, F>(a, S, xw, xin, y0, dA, mA, qxA, qyA), kB;
+    int y = y0;
+    for (;;) {
+        if (y >= y1) break;
+        row_issue<ST, BC>(a, S, xw, y + 1, dB);
+        halo_q<ST, BC, F>(a, S, hxw, hxin, y, qhl, qhr);
+        kB = row_finish<ST, BC, F>(a, S, xw, xin, y + 1, dB, mB, qxB, qyB);
+        collide_store<ST, BC, F>(a, D, dA, mA, kA, lane, qxA, qhl, qhr, qyp, qyB, owned, vo);
+        qyp = qyA;
+        ++y;
+        vo += pitch_b;
+        if (y >= y1) break;
+        row_issue<ST, BC>(a, S, xw, y + 1, dA);
+        halo_q<ST, BC, F>(a, S, hxw, hxin, y, qhl, qhr);
+        kA = row_finish<ST, BC, F>(a, S, xw, xin, y + 1, dA, mA, qxA, qyA);
+        collide_store<ST, BC, F>(a, D, dB, mB, kB, lane, qxB, qhl, qhr, qyp, qyA, owned, vo);
+        qyp = qyB;
+        ++y;
+        vo += pitch_b;
     }
 }
 
@@ -575,7 +723,8 @@ __global__ __launch_bounds__(kBlock) void k_init(const KArgs a, const float *__r
     m.jy = m.rho * m.uy;
     m.sf = m.sx = m.sy = 0.f;
     float fe[9], he[9];
-    equilibria(a, m, fe, he);
+    equilibria<Dyn>(a, m, fe, he);
+    const Planes D = planes(dst, a.plane_bytes);
     const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
     const int ey[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 #pragma unroll
@@ -589,9 +738,9 @@ __global__ __launch_bounds__(kBlock) void k_init(const KArgs a, const float *__r
             if (!a.per_y) continue;
             ty += (ty < 0) ? a.ny : -a.ny;
         }
-        const unsigned t = (unsigned)ty * a.pitch + tx;
-        Codec<ST>::st(wplane<ST>(dst, a.plane_bytes, q), t, fe[q], q);
-        Codec<ST>::st(wplane<ST>(dst, a.plane_bytes, 9 + q), t, he[q], 9 + q);
+        const unsigned t = ((unsigned)ty * a.pitch + tx) * Codec<ST>::bytes;
+        Codec<ST>::st(D, t, fe[q], q, plane_bits(hash32(t ^ 0x5bd1e995u), q));
+        Codec<ST>::st(D, t, he[q], 9 + q, plane_bits(hash32(t ^ 0x5bd1e995u), 9 + q));
     }
 }
 
@@ -606,7 +755,7 @@ __global__ __launch_bounds__(kBlock) void k_macros(const KArgs a, const char *__
     const int x = i % a.nx, y = i / a.nx;
     float d[18];
     Mom m;
-    node_state<ST, BC>(a, src, x, y, d, m);
+    node_state<ST, BC>(a, planes(src, a.plane_bytes), x, y, d, m);
     const unsigned k = (unsigned)y * opitch + x;
     if (o0) o0[k] = full ? m.rho : m.drho;
     if (o1) o1[k] = m.ux;
@@ -623,7 +772,7 @@ __global__ __launch_bounds__(kBlock) void k_pops(const KArgs a, const char *__re
     const int x = i % a.nx, y = i / a.nx;
     float d[18];
     Mom m;
-    node_state<ST, BC>(a, src, x, y, d, m);
+    node_state<ST, BC>(a, planes(src, a.plane_bytes), x, y, d, m);
     const unsigned k = (unsigned)y * a.pitch + x;
 #pragma unroll
     for (int q = 0; q < 18; ++q)
@@ -643,11 +792,12 @@ __global__ __launch_bounds__(kBlock) void k_diag(const KArgs a, const char *__re
                                                  int use_snap, int write_snap, double *__restrict__ partials) {
     double acc[kNred] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int n = a.nx * a.ny;
+    const Planes P = planes(src, a.plane_bytes);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const int x = i % a.nx, y = i / a.nx;
         float d[18];
         Mom m;
-        node_state<ST, BC>(a, src, x, y, d, m);
+        node_state<ST, BC>(a, planes(src, a.plane_bytes), x, y, d, m);
         double sf = 0, sh = 0;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -729,7 +879,7 @@ Layout layout_of(const lb_params *p) {
     Layout L;
     L.ssize = p->storage == LB_STORE_F32 ? 4 : 2;
     L.pitch = (int)align_up((size_t)p->nx, 64);
-    L.plane_elems = (size_t)L.pitch * p->ny + kPlanePad;
+    L.plane_elems = (size_t)L.pitch * p->ny + kPlanePadBytes / L.ssize;
     L.plane_bytes = L.plane_elems * L.ssize;
     L.pops_bytes = align_up(18 * L.plane_bytes, 256);
     L.snap_off = 2 * L.pops_bytes;
@@ -745,8 +895,11 @@ bool side_bounded(int k) { return k != LB_BC_PERIODIC; }
 lb_status validate(const lb_params *p) {
     if (!p) return fail(LB_EINVAL, "null parameters");
     if (p->nx < 1 || p->ny < 1) return fail(LB_EINVAL, "nx and ny must be >= 1");
-    if ((double)align_up((size_t)p->nx, 64) * p->ny > (double)(1u << 28))
-        return fail(LB_EINVAL, "grid too large (more than 2^28 nodes per plane)");
+    {
+        const double plane = (double)align_up((size_t)p->nx, 64) * p->ny * (p->storage == LB_STORE_F32 ? 4.0 : 2.0) +
+                             kPlanePadBytes;
+        if (9.0 * plane >= 4294967296.0) return fail(LB_EINVAL, "grid too large (9 planes must span < 4 GiB)");
+    }
     if (p->storage < 0 || p->storage > 2) return fail(LB_EINVAL, "storage");
     if (p->energy < 0 || p->energy > 1) return fail(LB_EINVAL, "energy");
     if (p->collision < 0 || p->collision > 1) return fail(LB_EINVAL, "collision");
@@ -908,23 +1061,32 @@ void set_inlet(lb_handle *h, long n) {
     h->a.in_dth = (float)((gamma - 1.0) * U0 * s / cs);
 }
 
-template <int ST, bool BC>
+template <int ST, bool BC, class F>
 void launch_step(lb_handle *h) {
     const KArgs &a = h->a;
     const long long waves = (long long)a.tiles_x * a.n_strips;
     const int blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL((k_step<ST, BC>), dim3(blocks), dim3(kBlock), 0, h->stream, a, h->pops[h->cur],
+    hipLaunchKernelGGL((k_step<ST, BC, F>), dim3(blocks), dim3(kBlock), 0, h->stream, a, h->pops[h->cur],
                        h->pops[1 - h->cur]);
 }
 
 typedef void (*step_fn)(lb_handle *);
-step_fn pick_step(int st, int bc) {
-    static const step_fn tbl[3][2] = {
-        {launch_step<LB_STORE_F32, false>, launch_step<LB_STORE_F32, true>},
-        {launch_step<LB_STORE_F16, false>, launch_step<LB_STORE_F16, true>},
-        {launch_step<LB_STORE_BF16, false>, launch_step<LB_STORE_BF16, true>},
+// kind: 0 periodic with runtime switches, 1 bounded, 2 periodic main configuration
+step_fn pick_step(int st, int kind) {
+    static const step_fn tbl[3][3] = {
+        {launch_step<LB_STORE_F32, false, Dyn>, launch_step<LB_STORE_F32, true, Dyn>,
+         launch_step<LB_STORE_F32, false, Head>},
+        {launch_step<LB_STORE_F16, false, Dyn>, launch_step<LB_STORE_F16, true, Dyn>,
+         launch_step<LB_STORE_F16, false, Head>},
+        {launch_step<LB_STORE_BF16, false, Dyn>, launch_step<LB_STORE_BF16, true, Dyn>,
+         launch_step<LB_STORE_BF16, false, Head>},
     };
-    return tbl[st][bc];
+    return tbl[st][kind];
+}
+
+// the compile-time switch set Head applies
+bool is_head(const KArgs &a) {
+    return a.total && a.heat && a.coupled && a.corr && !a.has_force && !a.bgk && a.visc == LB_VISC_CONST_TAU;
 }
 
 template <int ST, bool BC>
@@ -1071,9 +1233,10 @@ lb_status lb_init(lb_handle *h, const double *rho, const double *ux, const doubl
 lb_status lb_step(lb_handle *h, long n) {
     if (!h) return fail(LB_EINVAL, "null handle");
     if (n < 0) return fail(LB_EINVAL, "negative step count");
-    const step_fn fn = pick_step(h->p.storage, h->bc);
+    const step_fn fn = pick_step(h->p.storage, h->bc ? 1 : (is_head(h->a) ? 2 : 0));
     for (long s = 0; s < n; ++s) {
         set_inlet(h, h->n);
+        h->a.step = (unsigned)h->n;
         fn(h);
         h->cur ^= 1;
         h->n += 1;
