@@ -170,6 +170,68 @@ void lb_destroy(lb_handle *h);
 /* Message of the last failed call on this thread ("" if none). */
 const char *lb_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of many grids (cavity or channel solves of
+ * uneven sizes) in one packed launch per time step.
+ *
+ * The caller hands the server one device pool; the server keeps the state of
+ * every admitted request resident in it and admits queued requests first in,
+ * first out as their byte footprint (lb_state_bytes) and a slot (at most 512
+ * resident grids) become free.  One lbs_advance call runs k steps of every
+ * resident grid as a hipGraph of k launches of one packed kernel (the same
+ * per-node step as lb_step), then reads every grid's FP64 convergence
+ * residual r = ||T - T_snap|| / ||T|| (snapshot k steps earlier) in one copy,
+ * retires grids that converged (r < tol), reached a plateau (no new minimum
+ * over 10 checks), hit max_steps or became unstable, stores their final
+ * fields on the host, frees their memory and admits waiting requests.
+ * Requests of one server share its storage type; inlet sides are not served.
+ * One server must not be used by two threads at once.
+ * ------------------------------------------------------------------------ */
+typedef struct lbs_server lbs_server;
+
+typedef enum {
+    LBS_QUEUED = 0,
+    LBS_RUNNING = 1,
+    LBS_CONVERGED = 2,
+    LBS_PLATEAU = 3,
+    LBS_STEP_CAP = 4,
+    LBS_UNSTABLE = 5
+} lbs_state;
+
+/* Bytes of the pool the server keeps for its slot and work tables. */
+size_t lbs_pool_overhead(void);
+
+/* Server over a caller-owned, 256-byte aligned device pool of pool_bytes
+ * bytes; storage is an lb_storage, k_steps the steps per batch. */
+lb_status lbs_create(void *dev_pool, size_t pool_bytes, int storage, int k_steps, void *hip_stream, lbs_server **out);
+
+/* Queues a request (host fields as in lb_init, NULL: rest state); *id
+ * receives its handle.  LB_ENOMEM when it cannot fit the pool at all. */
+lb_status lbs_submit(lbs_server *s, const lb_params *p, const double *rho, const double *ux, const double *uy,
+                     const double *T, double tol, long max_steps, long *id);
+
+/* Admission, one packed batch of k steps over all resident grids, residual
+ * checks, retirement and admission again.  Synchronises the stream.  Reports
+ * the resident and queued counts at the start of the batch. */
+lb_status lbs_advance(lbs_server *s, int *n_resident, int *n_queued);
+
+/* State (lbs_state), steps done, last residual and the submit, admit and
+ * finish times (seconds since lbs_create; -1 until reached) of a request. */
+lb_status lbs_poll(lbs_server *s, long id, int *state, long *steps, double *residual, double times[3]);
+
+/* Final fields of a finished request (LB_EBUSY while queued or running). */
+lb_status lbs_result(lbs_server *s, long id, double *rho, double *ux, double *uy, double *T);
+
+/* Forgets a finished request and its stored fields. */
+lb_status lbs_release(lbs_server *s, long id);
+
+/* out = {batches, node updates, seconds inside lbs_advance batches, finished
+ * requests, free pool bytes, queued requests}. */
+lb_status lbs_stats(lbs_server *s, double out[6]);
+
+/* Releases the server (not the caller's pool). */
+void lbs_destroy(lbs_server *s);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,9 +29,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -613,7 +616,7 @@ __device__ __forceinline__ int row_finish(const KArgs &a, const Planes &S, int x
 template <int ST, bool BC, class F>
 __device__ __forceinline__ void collide_store(const KArgs &a, const Planes &D, const float d[18], const Mom &m,
                                               int kind, int lane, float qxc, float qhl, float qhr, float qyp,
-                                              float qyn, bool owned, unsigned vo) {
+                                              float qyn, bool owned, unsigned vo, unsigned step) {
     float qxl = __shfl_up(qxc, 1), qxr = __shfl_down(qxc, 1);
     qxl = lane == 0 ? qhl : qxl;
     qxr = lane == kWave - 1 ? qhr : qxr;
@@ -623,7 +626,7 @@ __device__ __forceinline__ void collide_store(const KArgs &a, const Planes &D, c
     float o[18];
     collide<F>(a, d, m, kind, phix, phiy, o);
     if (owned) {
-        const unsigned h = ST == LB_STORE_F32 ? 0u : hash32((vo / Codec<ST>::bytes) ^ (a.step * 0x9E3779B9u));
+        const unsigned h = ST == LB_STORE_F32 ? 0u : hash32((vo / Codec<ST>::bytes) ^ (step * 0x9E3779B9u));
 #pragma unroll
         for (int q = 0; q < 18; ++q) Codec<ST>::st(D, vo, o[q], q, plane_bits(h, q));
     }
@@ -656,14 +659,12 @@ __device__ __forceinline__ int col_wrap(const KArgs &a, int x, bool &xin) {
     return min(max(x, 0), a.nx - 1);
 }
 
-// ----------------------------------------------------------------- kernels
+// One wavefront's strip: 64 aligned columns from x0 = 64 tx, rows
+// [R sy, R sy + R).  Shared by the single-grid and the packed (serving) step.
 template <int ST, bool BC, class F>
-__global__ __launch_bounds__(kBlock) void k_step(const KArgs a, const char *__restrict__ src, char *__restrict__ dst) {
+__device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict__ src, char *__restrict__ dst,
+                                          int tx, int sy, unsigned step) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-    const int wv = blk * kWavesPerBlock + (threadIdx.x >> 6);
-    if (wv >= a.tiles_x * a.n_strips) return;
-    const int tx = wv % a.tiles_x, sy = wv / a.tiles_x;
     const int x0 = tx * kTile, gx = x0 + lane;
     bool xin, hxin;
     const int xw = col_wrap(a, gx, xin);
@@ -689,7 +690,7 @@ __global__ __launch_bounds__(kBlock) void k_step(const KArgs a, const char *__re
         row_issue<ST, BC>(a, S, xw, y + 1, dB);
         halo_q<ST, BC, F>(a, S, hxw, hxin, y, qhl, qhr);
         kB = row_finish<ST, BC, F>(a, S, xw, xin, y + 1, dB, mB, qxB, qyB);
-        collide_store<ST, BC, F>(a, D, dA, mA, kA, lane, qxA, qhl, qhr, qyp, qyB, owned, vo);
+        collide_store<ST, BC, F>(a, D, dA, mA, kA, lane, qxA, qhl, qhr, qyp, qyB, owned, vo, step);
         qyp = qyA;
         ++y;
         vo += pitch_b;
@@ -697,10 +698,47 @@ __global__ __launch_bounds__(kBlock) void k_step(const KArgs a, const char *__re
         row_issue<ST, BC>(a, S, xw, y + 1, dA);
         halo_q<ST, BC, F>(a, S, hxw, hxin, y, qhl, qhr);
         kA = row_finish<ST, BC, F>(a, S, xw, xin, y + 1, dA, mA, qxA, qyA);
-        collide_store<ST, BC, F>(a, D, dB, mB, kB, lane, qxB, qhl, qhr, qyp, qyA, owned, vo);
+        collide_store<ST, BC, F>(a, D, dB, mB, kB, lane, qxB, qhl, qhr, qyp, qyA, owned, vo, step);
         qyp = qyB;
         ++y;
         vo += pitch_b;
+    }
+}
+
+// ----------------------------------------------------------------- kernels
+template <int ST, bool BC, class F>
+__global__ __launch_bounds__(kBlock) void k_step(const KArgs a, const char *__restrict__ src, char *__restrict__ dst) {
+    const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
+    const int wv = blk * kWavesPerBlock + (threadIdx.x >> 6);
+    if (wv >= a.tiles_x * a.n_strips) return;
+    run_strip<ST, BC, F>(a, src, dst, wv % a.tiles_x, wv / a.tiles_x, a.step);
+}
+
+// Packed step of many grids (serving): the work list holds one item per
+// wavefront strip of every resident grid; a fixed grid of wavefronts strides
+// over it.  Call i of a batch reads buffer (cur + i) & 1 of each grid.
+struct SlotDev {
+    KArgs a;
+    const char *pops[2];
+    int cur, pad_;
+    long long n;  // time step at the start of the batch
+};
+struct WorkItem {
+    int slot, tx, sy, pad_;
+};
+
+template <int ST>
+__global__ __launch_bounds__(kBlock) void k_step_multi(const SlotDev *__restrict__ slots,
+                                                       const WorkItem *__restrict__ items, const int *__restrict__ nitems,
+                                                       int i) {
+    const int nw = *nitems;
+    const int waves = gridDim.x * kWavesPerBlock;
+    for (int w = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); w < nw; w += waves) {
+        const WorkItem it = items[w];
+        const SlotDev &sd = slots[it.slot];
+        const int c = (sd.cur + i) & 1;
+        run_strip<ST, true, Dyn>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]), it.tx, it.sy,
+                                 (unsigned)(sd.n + i));
     }
 }
 
@@ -982,8 +1020,9 @@ void set_strip(lb_handle *h) {
     a.tiles_x = (a.nx + kTile - 1) / kTile;
     int R = h->strip_user;
     if (R <= 0) {
-        // enough wavefronts to fill 256 CUs several times over, long strips otherwise
-        R = 64;
+        // 16-row strips (measured best on 4096^2 and 8192^2); shorter ones when
+        // the grid would not give 256 CUs enough wavefronts
+        R = 16;
         while (R > 4 && (long long)a.tiles_x * ((a.ny + R - 1) / R) < 16384) R >>= 1;
     }
     a.strip_rows = R;
@@ -1111,6 +1150,14 @@ void launch_diag(lb_handle *h, int use_snap, int write_snap) {
     hipLaunchKernelGGL((k_diag<ST, BC>), dim3(h->red_blocks), dim3(kBlock), 0, h->stream, h->a, h->pops[h->cur],
                        h->snap, use_snap, write_snap, h->partials);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, h->stream, h->partials, h->red_blocks, h->red);
+}
+
+template <int ST, bool BC>
+void launch_diag_to(lb_handle *h, int use_snap, int write_snap, double *out) {
+    set_inlet(h, h->n);
+    hipLaunchKernelGGL((k_diag<ST, BC>), dim3(h->red_blocks), dim3(kBlock), 0, h->stream, h->a, h->pops[h->cur],
+                       h->snap, use_snap, write_snap, h->partials);
+    hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, h->stream, h->partials, h->red_blocks, out);
 }
 
 template <int ST>
@@ -1366,6 +1413,401 @@ lb_status lb_load(lb_handle *h, const void *host_buf) {
     h->n = (long)hdr[4];
     h->have_snap = (int)hdr[5];
     return LB_OK;
+}
+
+}  // extern "C"
+
+// =====================================================================
+// Serving: continuous batching of many grids in one packed launch
+// =====================================================================
+struct lbs_server;
+
+namespace {
+
+constexpr int kMaxSlots = 512;
+constexpr int kMaxItems = 1 << 18;
+constexpr int kMultiBlocks = 2048;  // fixed grid of the packed step: 8192 wavefronts
+
+double now_s() {
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
+
+struct Request {
+    long id = 0;
+    lb_params p{};
+    std::vector<double> init;  // 4 fields [4][ny][nx], empty: rest state
+    double tol = 0, best = INFINITY, residual = INFINITY;
+    long max_steps = 0, steps = 0;
+    int state = LBS_QUEUED, stall = 0, slot = -1;
+    size_t off = 0, bytes = 0;
+    double t_submit = 0, t_admit = -1, t_done = -1;
+    lb_handle *h = nullptr;
+    std::vector<double> result;  // 4 fields once finished
+};
+
+}  // namespace
+
+struct lbs_server {
+    char *pool = nullptr;
+    size_t pool_bytes = 0, hdr = 0;
+    hipStream_t stream = nullptr;
+    int storage = 0, k = 1;
+    double t0 = 0;
+    SlotDev *d_slots = nullptr;
+    WorkItem *d_items = nullptr;
+    int *d_nitems = nullptr;
+    double *d_results = nullptr;
+    std::vector<SlotDev> h_slots;
+    std::vector<WorkItem> h_items;
+    std::vector<double> h_results;
+    std::vector<long> slot_req;               // slot -> request id or -1
+    std::map<size_t, size_t> free_blocks;     // offset -> bytes
+    std::map<long, Request> reqs;
+    std::deque<long> queue;
+    long next_id = 1;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double batches = 0, node_updates = 0, busy_s = 0, completed = 0;
+};
+
+namespace {
+
+bool pool_alloc(lbs_server *S, size_t bytes, size_t &off) {
+    bytes = align_up(bytes, 256);
+    for (auto it = S->free_blocks.begin(); it != S->free_blocks.end(); ++it) {
+        if (it->second >= bytes) {
+            off = it->first;
+            const size_t rest = it->second - bytes;
+            S->free_blocks.erase(it);
+            if (rest) S->free_blocks[off + bytes] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void pool_free(lbs_server *S, size_t off, size_t bytes) {
+    bytes = align_up(bytes, 256);
+    auto it = S->free_blocks.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != S->free_blocks.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        S->free_blocks.erase(nx);
+    }
+    if (it != S->free_blocks.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            S->free_blocks.erase(it);
+        }
+    }
+}
+
+lb_status build_graph(lbs_server *S) {
+    HIPCHK(hipGraphCreate(&S->graph, 0));
+    hipGraphNode_t prev = nullptr;
+    void *fn = nullptr;
+    switch (S->storage) {
+    case LB_STORE_F32: fn = (void *)k_step_multi<LB_STORE_F32>; break;
+    case LB_STORE_F16: fn = (void *)k_step_multi<LB_STORE_F16>; break;
+    default: fn = (void *)k_step_multi<LB_STORE_BF16>; break;
+    }
+    for (int i = 0; i < S->k; ++i) {
+        int ii = i;
+        const SlotDev *a0 = S->d_slots;
+        const WorkItem *a1 = S->d_items;
+        const int *a2 = S->d_nitems;
+        void *args[4] = {(void *)&a0, (void *)&a1, (void *)&a2, (void *)&ii};
+        hipKernelNodeParams kp{};
+        kp.func = fn;
+        kp.gridDim = dim3(kMultiBlocks);
+        kp.blockDim = dim3(kBlock);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        HIPCHK(hipGraphAddKernelNode(&node, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        prev = node;
+    }
+    HIPCHK(hipGraphInstantiate(&S->exec, S->graph, nullptr, nullptr, 0));
+    return LB_OK;
+}
+
+lb_status admit(lbs_server *S) {
+    while (!S->queue.empty()) {
+        Request &r = S->reqs[S->queue.front()];
+        int slot = -1;
+        for (int i = 0; i < kMaxSlots; ++i)
+            if (S->slot_req[i] < 0) {
+                slot = i;
+                break;
+            }
+        if (slot < 0) return LB_OK;
+        size_t off;
+        if (!pool_alloc(S, r.bytes, off)) return LB_OK;  // first in, first out: wait for memory
+        lb_handle *h = nullptr;
+        lb_status st = lb_create(&r.p, S->pool + off, r.bytes, S->stream, &h);
+        if (st != LB_OK) {
+            pool_free(S, off, r.bytes);
+            return st;
+        }
+        const size_t N = (size_t)r.p.nx * r.p.ny;
+        if (r.init.empty())
+            st = lb_init(h, nullptr, nullptr, nullptr, nullptr);
+        else
+            st = lb_init(h, r.init.data(), r.init.data() + N, r.init.data() + 2 * N, r.init.data() + 3 * N);
+        if (st != LB_OK) {
+            lb_destroy(h);
+            pool_free(S, off, r.bytes);
+            return st;
+        }
+        r.init.clear();
+        r.init.shrink_to_fit();
+        r.h = h;
+        r.off = off;
+        r.slot = slot;
+        r.state = LBS_RUNNING;
+        r.t_admit = now_s() - S->t0;
+        S->slot_req[slot] = r.id;
+        S->queue.pop_front();
+    }
+    return LB_OK;
+}
+
+lb_status retire(lbs_server *S, Request &r, int state) {
+    const size_t N = (size_t)r.p.nx * r.p.ny;
+    r.result.assign(4 * N, 0.0);
+    lb_status st = lb_macros(r.h, r.result.data(), r.result.data() + N, r.result.data() + 2 * N,
+                             r.result.data() + 3 * N);
+    r.state = state;
+    r.t_done = now_s() - S->t0;
+    S->slot_req[r.slot] = -1;
+    r.slot = -1;
+    lb_destroy(r.h);
+    r.h = nullptr;
+    pool_free(S, r.off, r.bytes);
+    S->completed += 1;
+    return st;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lbs_pool_overhead(void) {
+    return align_up(kMaxSlots * sizeof(SlotDev), 256) + align_up((size_t)kMaxItems * sizeof(WorkItem), 256) + 256 +
+           align_up(kMaxSlots * kNred * sizeof(double), 256);
+}
+
+lb_status lbs_create(void *dev_pool, size_t pool_bytes, int storage, int k_steps, void *hip_stream, lbs_server **out) {
+    if (!out) return fail(LB_EINVAL, "null output");
+    *out = nullptr;
+    if (!dev_pool || ((uintptr_t)dev_pool & 255)) return fail(LB_EINVAL, "pool must be a 256-byte aligned device buffer");
+    if (storage < 0 || storage > 2) return fail(LB_EINVAL, "storage");
+    if (k_steps < 1 || k_steps > 100000) return fail(LB_EINVAL, "k_steps must lie in 1..100000");
+    const size_t hdr = lbs_pool_overhead();
+    if (pool_bytes <= hdr) return fail(LB_ENOMEM, "pool smaller than the server tables");
+    lbs_server *S = new lbs_server();
+    S->pool = (char *)dev_pool;
+    S->pool_bytes = pool_bytes;
+    S->hdr = hdr;
+    S->stream = (hipStream_t)hip_stream;
+    S->storage = storage;
+    S->k = k_steps;
+    S->t0 = now_s();
+    char *p = S->pool;
+    S->d_slots = (SlotDev *)p;
+    p += align_up(kMaxSlots * sizeof(SlotDev), 256);
+    S->d_items = (WorkItem *)p;
+    p += align_up((size_t)kMaxItems * sizeof(WorkItem), 256);
+    S->d_nitems = (int *)p;
+    p += 256;
+    S->d_results = (double *)p;
+    S->h_slots.resize(kMaxSlots);
+    S->h_results.assign((size_t)kMaxSlots * kNred, 0.0);
+    S->slot_req.assign(kMaxSlots, -1);
+    S->free_blocks[hdr] = (pool_bytes - hdr) / 256 * 256;
+    lb_status st = build_graph(S);
+    if (st != LB_OK) {
+        delete S;
+        return st;
+    }
+    *out = S;
+    return LB_OK;
+}
+
+lb_status lbs_submit(lbs_server *S, const lb_params *p, const double *rho, const double *ux, const double *uy,
+                     const double *T, double tol, long max_steps, long *id) {
+    if (!S || !p || !id) return fail(LB_EINVAL, "null argument");
+    lb_status st = validate(p);
+    if (st != LB_OK) return st;
+    if (p->storage != S->storage) return fail(LB_EINVAL, "request storage differs from the server's");
+    if (p->side[0].kind == LB_BC_INLET) return fail(LB_EINVAL, "the packed step serves grids without an inlet");
+    if (max_steps < 1) return fail(LB_EINVAL, "max_steps must be >= 1");
+    const Layout L = layout_of(p);
+    if (L.total > S->pool_bytes - S->hdr) return fail(LB_ENOMEM, "request larger than the pool");
+    Request r;
+    r.id = S->next_id++;
+    r.p = *p;
+    r.tol = tol;
+    r.max_steps = max_steps;
+    r.bytes = L.total;
+    r.t_submit = now_s() - S->t0;
+    if (rho || ux || uy || T) {
+        const size_t N = (size_t)p->nx * p->ny;
+        r.init.resize(4 * N);
+        for (size_t i = 0; i < N; ++i) {
+            r.init[i] = rho ? rho[i] : p->rho0;
+            r.init[N + i] = ux ? ux[i] : 0.0;
+            r.init[2 * N + i] = uy ? uy[i] : 0.0;
+            r.init[3 * N + i] = T ? T[i] : p->T0;
+        }
+    }
+    S->reqs[r.id] = std::move(r);
+    S->queue.push_back(S->next_id - 1);
+    *id = S->next_id - 1;
+    return LB_OK;
+}
+
+lb_status lbs_advance(lbs_server *S, int *n_resident, int *n_queued) {
+    if (!S) return fail(LB_EINVAL, "null server");
+    lb_status st = admit(S);
+    if (st != LB_OK) return st;
+    // work list of every resident grid
+    S->h_items.clear();
+    std::vector<int> live;
+    for (int slot = 0; slot < kMaxSlots; ++slot) {
+        if (S->slot_req[slot] < 0) continue;
+        Request &r = S->reqs[S->slot_req[slot]];
+        lb_handle *h = r.h;
+        SlotDev &sd = S->h_slots[slot];
+        sd.a = h->a;
+        sd.pops[0] = h->pops[0];
+        sd.pops[1] = h->pops[1];
+        sd.cur = h->cur;
+        sd.n = h->n;
+        for (int sy = 0; sy < h->a.n_strips; ++sy)
+            for (int tx = 0; tx < h->a.tiles_x; ++tx) S->h_items.push_back(WorkItem{slot, tx, sy, 0});
+        live.push_back(slot);
+    }
+    if (n_resident) *n_resident = (int)live.size();
+    if (n_queued) *n_queued = (int)S->queue.size();
+    if (live.empty()) return LB_OK;
+    if ((int)S->h_items.size() > kMaxItems) return fail(LB_ENOMEM, "work list overflow");
+    const double t_start = now_s();
+    const int nitems = (int)S->h_items.size();
+    HIPCHK(hipMemcpyAsync(S->d_slots, S->h_slots.data(), kMaxSlots * sizeof(SlotDev), hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipMemcpyAsync(S->d_items, S->h_items.data(), nitems * sizeof(WorkItem), hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipMemcpyAsync(S->d_nitems, &nitems, sizeof(int), hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipGraphLaunch(S->exec, S->stream));
+    // advance the grids' clocks, then the FP64 residual of each grid in one read-back
+    for (int slot : live) {
+        Request &r = S->reqs[S->slot_req[slot]];
+        lb_handle *h = r.h;
+        h->cur ^= (S->k & 1);
+        h->n += S->k;
+        S->node_updates += (double)r.p.nx * r.p.ny * S->k;
+        double *out = S->d_results + (size_t)slot * kNred;
+        DISPATCH(h, launch_diag_to, h, h->have_snap, 1, out);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(S->h_results.data(), S->d_results, kMaxSlots * kNred * sizeof(double), hipMemcpyDeviceToHost,
+                          S->stream));
+    HIPCHK(hipStreamSynchronize(S->stream));
+    S->busy_s += now_s() - t_start;
+    S->batches += 1;
+    for (int slot : live) {
+        Request &r = S->reqs[S->slot_req[slot]];
+        lb_handle *h = r.h;
+        const double *res = &S->h_results[(size_t)slot * kNred];
+        r.residual = h->have_snap ? std::sqrt(res[5]) / std::sqrt(res[6]) : INFINITY;
+        h->have_snap = 1;
+        r.steps = h->n;
+        int done = -1;
+        if (res[4] > 0) {
+            done = LBS_UNSTABLE;
+        } else if (r.residual < r.tol) {
+            done = LBS_CONVERGED;
+        } else if (r.steps >= r.max_steps) {
+            done = LBS_STEP_CAP;
+        } else if (std::isfinite(r.residual)) {
+            // plateau: no new minimum over 10 consecutive checks
+            if (r.residual < r.best) {
+                r.best = r.residual;
+                r.stall = 0;
+            } else if (++r.stall >= 10) {
+                done = LBS_PLATEAU;
+            }
+        }
+        if (done >= 0) {
+            st = retire(S, r, done);
+            if (st != LB_OK) return st;
+        }
+    }
+    return admit(S);
+}
+
+lb_status lbs_poll(lbs_server *S, long id, int *state, long *steps, double *residual, double times[3]) {
+    if (!S) return fail(LB_EINVAL, "null server");
+    auto it = S->reqs.find(id);
+    if (it == S->reqs.end()) return fail(LB_EINVAL, "unknown request id");
+    const Request &r = it->second;
+    if (state) *state = r.state;
+    if (steps) *steps = r.steps;
+    if (residual) *residual = r.residual;
+    if (times) {
+        times[0] = r.t_submit;
+        times[1] = r.t_admit;
+        times[2] = r.t_done;
+    }
+    return LB_OK;
+}
+
+lb_status lbs_result(lbs_server *S, long id, double *rho, double *ux, double *uy, double *T) {
+    if (!S) return fail(LB_EINVAL, "null server");
+    auto it = S->reqs.find(id);
+    if (it == S->reqs.end()) return fail(LB_EINVAL, "unknown request id");
+    const Request &r = it->second;
+    if (r.result.empty()) return fail(LB_EBUSY, "request not finished");
+    const size_t N = (size_t)r.p.nx * r.p.ny;
+    if (rho) std::memcpy(rho, r.result.data(), N * sizeof(double));
+    if (ux) std::memcpy(ux, r.result.data() + N, N * sizeof(double));
+    if (uy) std::memcpy(uy, r.result.data() + 2 * N, N * sizeof(double));
+    if (T) std::memcpy(T, r.result.data() + 3 * N, N * sizeof(double));
+    return LB_OK;
+}
+
+lb_status lbs_release(lbs_server *S, long id) {
+    if (!S) return fail(LB_EINVAL, "null server");
+    auto it = S->reqs.find(id);
+    if (it == S->reqs.end()) return fail(LB_EINVAL, "unknown request id");
+    if (it->second.state == LBS_QUEUED || it->second.state == LBS_RUNNING)
+        return fail(LB_EBUSY, "request still queued or running");
+    S->reqs.erase(it);
+    return LB_OK;
+}
+
+lb_status lbs_stats(lbs_server *S, double out[6]) {
+    if (!S || !out) return fail(LB_EINVAL, "null argument");
+    size_t free_b = 0;
+    for (auto &b : S->free_blocks) free_b += b.second;
+    out[0] = S->batches;
+    out[1] = S->node_updates;
+    out[2] = S->busy_s;
+    out[3] = S->completed;
+    out[4] = (double)free_b;
+    out[5] = (double)S->queue.size();
+    return LB_OK;
+}
+
+void lbs_destroy(lbs_server *S) {
+    if (!S) return;
+    for (auto &kv : S->reqs)
+        if (kv.second.h) lb_destroy(kv.second.h);
+    if (S->exec) (void)hipGraphExecDestroy(S->exec);
+    if (S->graph) (void)hipGraphDestroy(S->graph);
+    delete S;
 }
 
 }  // extern "C"

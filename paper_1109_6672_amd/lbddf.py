@@ -73,7 +73,19 @@ _SIGS = {
     "lb_stream": (C.c_void_p, [C.c_void_p]),
     "lb_destroy": (None, [C.c_void_p]),
     "lb_last_error": (C.c_char_p, []),
+    "lbs_pool_overhead": (C.c_size_t, []),
+    "lbs_create": (C.c_int, [C.c_void_p, C.c_size_t, C.c_int, C.c_int, C.c_void_p, C.POINTER(C.c_void_p)]),
+    "lbs_submit": (C.c_int, [C.c_void_p, C.POINTER(lb_params), _D, _D, _D, _D, C.c_double, C.c_long,
+                             C.POINTER(C.c_long)]),
+    "lbs_advance": (C.c_int, [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+    "lbs_poll": (C.c_int, [C.c_void_p, C.c_long, C.POINTER(C.c_int), C.POINTER(C.c_long), _D, _D]),
+    "lbs_result": (C.c_int, [C.c_void_p, C.c_long, _D, _D, _D, _D]),
+    "lbs_release": (C.c_int, [C.c_void_p, C.c_long]),
+    "lbs_stats": (C.c_int, [C.c_void_p, _D]),
+    "lbs_destroy": (None, [C.c_void_p]),
 }
+
+LBS_STATES = {0: "queued", 1: "running", 2: "converged", 3: "plateau", 4: "step_cap", 5: "unstable"}
 
 
 def load():
@@ -234,3 +246,77 @@ class Solver:
     @property
     def strip_rows(self) -> int:
         return int(self.lib.lb_strip_rows(self.h))
+
+
+class Server:
+    """Continuous-batching server over one device pool (the lbs_* calls)."""
+
+    def __init__(self, pool_bytes: int, storage: str = "f32", k_steps: int = 100, device: int = 0, stream=None):
+        import torch
+
+        self.lib = load()
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        with torch.cuda.device(self.device):
+            self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
+        h = C.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.lbs_create(C.c_void_p(self.pool.data_ptr()), C.c_size_t(int(pool_bytes)),
+                                       _STORAGE[storage], int(k_steps), C.c_void_p(self.stream.cuda_stream),
+                                       C.byref(h)))
+        self.h = h
+        self.storage = storage
+        self.k = int(k_steps)
+        self.shapes = {}
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.lbs_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def submit(self, params: dict, fields=None, tol: float = 1e-8, max_steps: int = 10 ** 6) -> int:
+        p = dict(params, storage=self.storage)
+        s = make_params(p)
+        n = int(p["nx"]) * int(p["ny"])
+        arrs = [None] * 4 if fields is None else [
+            None if a is None else np.ascontiguousarray(a, dtype=np.float64).reshape(-1) for a in fields]
+        for a in arrs:
+            assert a is None or a.size == n
+        rid = C.c_long()
+        _check(self.lib.lbs_submit(self.h, C.byref(s), *[_dptr(a) for a in arrs], float(tol), int(max_steps),
+                                   C.byref(rid)))
+        self.shapes[rid.value] = (int(p["ny"]), int(p["nx"]))
+        return rid.value
+
+    def advance(self):
+        r, q = C.c_int(), C.c_int()
+        _check(self.lib.lbs_advance(self.h, C.byref(r), C.byref(q)))
+        return r.value, q.value
+
+    def poll(self, rid: int) -> dict:
+        st, steps, res, t = C.c_int(), C.c_long(), np.zeros(1), np.zeros(3)
+        _check(self.lib.lbs_poll(self.h, int(rid), C.byref(st), C.byref(steps), _dptr(res), _dptr(t)))
+        return dict(state=LBS_STATES[st.value], steps=steps.value, residual=float(res[0]), t_submit=t[0],
+                    t_admit=t[1], t_done=t[2])
+
+    def result(self, rid: int):
+        ny, nx = self.shapes[rid]
+        out = [np.empty((ny, nx)) for _ in range(4)]
+        _check(self.lib.lbs_result(self.h, int(rid), *[_dptr(a) for a in out]))
+        return tuple(out)
+
+    def release(self, rid: int):
+        _check(self.lib.lbs_release(self.h, int(rid)))
+        self.shapes.pop(rid, None)
+
+    def stats(self) -> dict:
+        o = np.zeros(6)
+        _check(self.lib.lbs_stats(self.h, _dptr(o)))
+        return dict(batches=int(o[0]), node_updates=o[1], busy_s=o[2], finished=int(o[3]), free_bytes=int(o[4]),
+                    queued=int(o[5]))

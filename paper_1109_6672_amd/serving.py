@@ -1,0 +1,91 @@
+"""Request loop over the continuous-batching server, and the one-solve-at-a-time
+baseline it is compared with (same kernels, one grid per launch, first in
+first out).  Both report per-request time-to-finish from the arrival time,
+p50/p99 latency, solves per second and aggregate MLUPS."""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import lbddf, workloads as W
+
+
+def _summary(lat, node_updates, wall, states):
+    lat = np.array(lat) if lat else np.zeros(1)
+    return dict(n=len(states), p50_s=float(np.percentile(lat, 50)), p99_s=float(np.percentile(lat, 99)),
+                solves_per_s=len(states) / wall, mlups=node_updates / wall / 1e6, wall_s=wall,
+                states={s: states.count(s) for s in set(states)})
+
+
+def run_server(requests, pool_bytes, storage="f32", k_steps=200, tol=1e-6, max_steps=20000, realtime=True):
+    """Drives a Server with the requests' arrival times (seconds from start)."""
+    srv = lbddf.Server(pool_bytes, storage=storage, k_steps=k_steps)
+    pending = sorted(requests, key=lambda r: r["t"])
+    ids, i = {}, 0
+    t0 = time.perf_counter()
+    while i < len(pending) or any(srv.poll(rid)["state"] in ("queued", "running") for rid in ids):
+        now = time.perf_counter() - t0
+        while i < len(pending) and (pending[i]["t"] <= now or not realtime):
+            r = pending[i]
+            ids[srv.submit(r["params"], r.get("fields"), tol=tol, max_steps=max_steps)] = r
+            i += 1
+        resident, queued = srv.advance()
+        if resident == 0 and queued == 0 and i < len(pending):
+            time.sleep(max(0.0, min(0.01, pending[i]["t"] - (time.perf_counter() - t0))))
+    wall = time.perf_counter() - t0
+    lat, states, nodes = [], [], 0.0
+    for rid, r in ids.items():
+        p = srv.poll(rid)
+        lat.append(p["t_done"] - (r["t"] if realtime else p["t_submit"]))
+        states.append(p["state"])
+        nodes += r["params"]["nx"] * r["params"]["ny"] * p["steps"]
+    out = _summary(lat, nodes, wall, states)
+    out["server"] = srv.stats()
+    return out, srv, ids
+
+
+def run_sequential(requests, storage="f32", k_steps=200, tol=1e-6, max_steps=20000, realtime=True):
+    """One solve at a time, first in first out, one grid per launch."""
+    pending = sorted(requests, key=lambda r: r["t"])
+    t0 = time.perf_counter()
+    lat, states, nodes = [], [], 0.0
+    for r in pending:
+        now = time.perf_counter() - t0
+        if realtime and r["t"] > now:
+            time.sleep(r["t"] - now)
+        p = dict(r["params"], storage=storage)
+        s = lbddf.Solver(p)
+        f = r.get("fields")
+        s.init(*(f if f is not None else (None,) * 4))
+        s.residual(update=True)
+        best, stall, state = np.inf, 0, "step_cap"
+        while s.time < max_steps:
+            s.step(k_steps)
+            d = s.diag(check=False)
+            if d["bad"]:
+                state = "unstable"
+                break
+            res = s.residual(update=True)
+            if res < tol:
+                state = "converged"
+                break
+            if res < best:
+                best, stall = res, 0
+            else:
+                stall += 1
+                if stall >= 10:
+                    state = "plateau"
+                    break
+        s.macros()
+        done = time.perf_counter() - t0
+        lat.append(done - (r["t"] if realtime else 0.0))
+        states.append(state)
+        nodes += p["nx"] * p["ny"] * s.time
+        s.close()
+    wall = time.perf_counter() - t0
+    return _summary(lat, nodes, wall, states)
+
+
+def mix(n_requests=32, sizes=(64, 128, 256), rate=50.0, storage="f32"):
+    return W.serving_mix(n_requests, sizes=sizes, rate=rate, storage=storage)

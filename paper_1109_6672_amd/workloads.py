@@ -243,3 +243,34 @@ def conduction_fields(p: dict, amp: float = 1e-6, k: int = 3):
     T[:, 1:-1] += p["T0"] * amp * (2.0 * u[:, 1:-1] - 1.0)
     rho = p["rho0"] * p["T0"] / T
     return rho, np.zeros((ny, nx)), np.zeros((ny, nx)), T
+
+
+def serving_mix(n_requests: int, sizes=(64, 128, 256, 512, 1024), Ra_range=(1e3, 1e6), dT_range=(0.02, 1.2),
+                rate: float = 50.0, Pr: float = 0.71, storage: str = "f32", k: int = 5, u_target: float = 0.05,
+                tau_min: float = 0.56):
+    """Seeded stream of cavity requests with Poisson arrivals.
+
+    Per request, from one SplitMix64 stream (seed SEED_BASE + k): the
+    exponential arrival gap (rate per second), the grid edge (uniform over
+    `sizes`), Ra (log-uniform) and dT/T0 (uniform).  The viscosity is chosen
+    so that the buoyancy velocity nu sqrt(Ra / Pr) / H equals `u_target`,
+    with tau_f(T_r) = 3 nu + 1/2 kept >= tau_min (requests at that bound are
+    flagged "under_resolved"); large dT uses the Sutherland law.  Returns a
+    list of dicts with keys t (arrival, s), params, n, Ra, dT, flags.
+    """
+    u = uniform01(SEED_BASE + k, 4 * n_requests).reshape(n_requests, 4)
+    out, t = [], 0.0
+    for i in range(n_requests):
+        t += -math.log(1.0 - u[i, 0]) / rate
+        n = int(sizes[min(int(u[i, 1] * len(sizes)), len(sizes) - 1)])
+        Ra = 10.0 ** (math.log10(Ra_range[0]) + u[i, 2] * (math.log10(Ra_range[1]) - math.log10(Ra_range[0])))
+        dT = dT_range[0] + u[i, 3] * (dT_range[1] - dT_range[0])
+        H = n - 1
+        nu = u_target * H * math.sqrt(Pr / Ra)
+        flags = []
+        if 3 * nu + 0.5 < tau_min:
+            nu = (tau_min - 0.5) / 3
+            flags.append("under_resolved")
+        p = cavity(n, Ra, dT, nu, Pr=Pr, sutherland=dT > 0.2, storage=storage)
+        out.append(dict(t=t, params=p, n=n, Ra=Ra, dT=dT, flags=flags))
+    return out

@@ -82,3 +82,13 @@ def test_workload_recipes_validate():
     for p in (W.couette(), W.cavity(128, 1e4, 0.02, 0.02), W.cavity(64, 1e5, 1.2, 0.01, sutherland=True),
               W.periodic(1024), W.channel(), W.couette_paper(1, 0.35)):
         lbddf.validate(p)
+
+
+def test_server_rejects_bad_pools_without_touching_the_device():
+    lib = lbddf.load()
+    h = C.c_void_p()
+    assert lib.lbs_create(None, 1 << 30, 0, 10, None, C.byref(h)) == lbddf.LB_EINVAL
+    assert lib.lbs_create(C.c_void_p(256), 1024, 0, 10, None, C.byref(h)) == lbddf.LB_ENOMEM
+    assert lib.lbs_create(C.c_void_p(256), 1 << 30, 7, 10, None, C.byref(h)) == lbddf.LB_EINVAL
+    assert lib.lbs_create(C.c_void_p(256), 1 << 30, 0, 0, None, C.byref(h)) == lbddf.LB_EINVAL
+    assert not h.value

@@ -1,0 +1,115 @@
+"""Continuous-batching server (lbs_*): results equal the single-grid path and
+are the same alone and in a mix; admission follows the pool's byte budget;
+a diverging request is retired without disturbing the others."""
+import numpy as np
+import pytest
+
+from paper_1109_6672_amd import lbddf, workloads as W
+from tests.gpu_common import rel_errors
+
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    return [
+        (W.cavity(40, 1e4, 0.1, 0.05), "noise"),
+        (W.cavity(70, 1e4, 0.02, 0.02), "noise"),
+        (W.cavity(66, 1e5, 1.2, 0.06, sutherland=True), "conduction"),
+        (W.cavity(100, 1e3, 0.3, 0.1, sutherland=True), "conduction"),
+    ]
+
+
+def _fields(p, kind):
+    return W.noisy_temperature_fields(p) if kind == "noise" else W.conduction_fields(p)
+
+
+def _run_to_end(srv, max_batches=1000):
+    for _ in range(max_batches):
+        r, q = srv.advance()
+        if r == 0 and q == 0:
+            return
+    raise AssertionError("server did not drain")
+
+
+def _pool(reqs, extra=1):
+    return lbddf.load().lbs_pool_overhead() + sum(lbddf.state_bytes(p) + 256 for p, _ in reqs) * extra
+
+
+def test_server_matches_single_grid(gpu):
+    reqs = _requests()
+    srv = lbddf.Server(_pool(reqs), k_steps=100)
+    ids = [srv.submit(p, _fields(p, k), tol=0.0, max_steps=600) for p, k in reqs]
+    _run_to_end(srv)
+    for rid, (p, k) in zip(ids, reqs):
+        st = srv.poll(rid)
+        assert st["state"] == "step_cap" and st["steps"] == 600, st
+        s = lbddf.Solver(p).init(*_fields(p, k)).step(600)
+        e = rel_errors(srv.result(rid), s.macros())
+        print(f"[case] server vs single grid {p['nx']}x{p['ny']}: {e}")
+        assert max(e) < 1e-6
+
+
+def test_alone_and_in_the_mix_are_identical(gpu):
+    reqs = _requests()
+    target = 1
+    alone = lbddf.Server(_pool(reqs), k_steps=50)
+    a = alone.submit(reqs[target][0], _fields(*reqs[target]), tol=0.0, max_steps=400)
+    _run_to_end(alone)
+    mixed = lbddf.Server(_pool(reqs), k_steps=50)
+    ids = [mixed.submit(p, _fields(p, k), tol=0.0, max_steps=400 if i == target else 200 + 100 * i)
+           for i, (p, k) in enumerate(reqs)]
+    _run_to_end(mixed)
+    for x, y in zip(alone.result(a), mixed.result(ids[target])):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_admission_follows_the_byte_budget(gpu):
+    reqs = _requests()
+    biggest = max(lbddf.state_bytes(p) for p, _ in reqs)
+    # room for the two largest at once (or a few smaller ones), not for all eight
+    pool = lbddf.load().lbs_pool_overhead() + 2 * (biggest + 256)
+    srv = lbddf.Server(pool, k_steps=100)
+    ids = [srv.submit(p, _fields(p, k), tol=0.0, max_steps=300) for p, k in reqs * 2]
+    max_res, saw_queue = 0, False
+    for _ in range(1000):
+        r, q = srv.advance()
+        max_res = max(max_res, r)
+        saw_queue |= q > 0
+        if r == 0 and q == 0:
+            break
+    footprints = sorted(lbddf.state_bytes(p) + 256 for p, _ in reqs)
+    fit = max(n for n in range(1, len(footprints) + 1) if sum(footprints[:n]) <= pool - lbddf.load().lbs_pool_overhead())
+    assert saw_queue and 1 <= max_res <= fit < 8
+    assert all(srv.poll(i)["state"] == "step_cap" for i in ids)
+    st = srv.stats()
+    assert st["free_bytes"] == pool - lbddf.load().lbs_pool_overhead() - (pool - lbddf.load().lbs_pool_overhead()) % 256
+
+
+def test_a_diverging_request_is_isolated(gpu):
+    good = W.cavity(40, 1e4, 0.1, 0.05)
+    bad = W.cavity(66, 1e5, 1.2, 0.01, sutherland=True)  # impulsive start: diverges within ~200 steps
+    ref = lbddf.Server(_pool([(good, 0)]), k_steps=50)
+    g0 = ref.submit(good, W.noisy_temperature_fields(good), tol=0.0, max_steps=600)
+    _run_to_end(ref)
+    srv = lbddf.Server(_pool([(good, 0), (bad, 0)]), k_steps=50)
+    b = srv.submit(bad, W.noisy_temperature_fields(bad), tol=0.0, max_steps=600)
+    g = srv.submit(good, W.noisy_temperature_fields(good), tol=0.0, max_steps=600)
+    _run_to_end(srv)
+    assert srv.poll(b)["state"] == "unstable" and srv.poll(b)["steps"] < 600
+    assert srv.poll(g)["state"] == "step_cap"
+    for x, y in zip(ref.result(g0), srv.result(g)):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_convergence_and_release(gpu):
+    p = W.cavity(33, 1e3, 0.1, 0.1)
+    srv = lbddf.Server(_pool([(p, 0)]), k_steps=500)
+    rid = srv.submit(p, W.conduction_fields(p), tol=1e-5, max_steps=200000)
+    _run_to_end(srv)
+    st = srv.poll(rid)
+    print(f"[case] convergence: {st}")
+    assert st["state"] in ("converged", "plateau") and st["residual"] < 1e-4
+    assert st["t_submit"] <= st["t_admit"] <= st["t_done"]
+    srv.release(rid)
+    with pytest.raises(lbddf.LBError):
+        srv.poll(rid)
