@@ -101,6 +101,28 @@ def cpu_baseline(seconds: float):
                 sample=f"periodic {n}x{n}, same recipe, {steps} steps in {t:.1f} s (FP64, OpenMP over rows)")
 
 
+def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 200):
+    """The continuous-batching server against one solve per launch, on the
+    same seeded stream of cavity requests (Poisson arrivals, 50 per second)."""
+    from paper_1109_6672_amd import lbddf, serving as SV, workloads as W
+
+    reqs = W.serving_mix(n_requests, sizes=sizes, rate=50.0)
+    pool = lbddf.load().lbs_pool_overhead() + sum(lbddf.state_bytes(r["params"]) + 256 for r in reqs)
+    packed, srv, _ = SV.run_server(reqs, pool, k_steps=k_steps, tol=1e-6, max_steps=20000)
+    srv.close()
+    seq = SV.run_sequential(reqs, k_steps=k_steps, tol=1e-6, max_steps=20000)
+    keep = ("p50_s", "p99_s", "solves_per_s", "mlups", "wall_s", "states")
+    return {
+        "workload": f"{n_requests} differentially heated cavity requests, edges {'/'.join(map(str, sizes))}, "
+                    "Poisson arrivals 50/s, Ra log-uniform 1e3..1e6, dT/T0 uniform 0.02..1.2, FP32, "
+                    f"residual checked every {k_steps} steps, tol 1e-6, cap 20000 steps",
+        "packed": {k: packed[k] for k in keep},
+        "one_at_a_time": {k: seq[k] for k in keep},
+        "solves_per_s_ratio": packed["solves_per_s"] / seq["solves_per_s"],
+        "p99_ratio": seq["p99_s"] / packed["p99_s"],
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -110,6 +132,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit and smaller-grid runs")
+    ap.add_argument("--no-serving", action="store_true", help="skip the packed-server comparison")
     ap.add_argument("--only", default="", help="storage of a single run (profiling): f32 | f16 | bf16")
     ap.add_argument("--copy-only", action="store_true",
                     help="HBM counter calibration: 5 plain device copies of 2 GiB (torch copy kernel)")
@@ -177,6 +200,10 @@ def main():
         "extra": extra,
         "bad_nodes": head["bad_nodes"],
     }
+    if not args.no_serving:
+        line["serving"] = serving_compare()
+        print(f"# serving: {line['serving']['packed']['solves_per_s']:.1f} solves/s packed, "
+              f"{line['serving']['one_at_a_time']['solves_per_s']:.1f} one at a time", file=sys.stderr, flush=True)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
     print(json.dumps(line), flush=True)

@@ -13,11 +13,12 @@
 //    the collision and the codec all work on these deviations, which keeps
 //    FP32 (and the 16-bit codecs) accurate for the small perturbations of
 //    low-Mach flows.
-//  * One wavefront owns a strip of 62 columns x R rows and marches up the
-//    strip.  Lanes 0 and 63 are halo columns; the x-neighbours of the
-//    correction term's Q (Eq. 48-50) come from the adjacent lanes, the
-//    y-neighbours from the previous and the look-ahead row kept in registers,
-//    so no LDS and no barrier is needed and each row is gathered once.
+//  * One wavefront owns a strip of 64 aligned columns x R rows and marches up
+//    the strip.  The x-neighbours of the correction term's Q (Eq. 48-50) come
+//    from the adjacent lanes, the y-neighbours from the previous and the
+//    look-ahead row kept in registers; the two columns just outside the tile
+//    are gathered for 32 rows at a time, one row per lane, and read out with
+//    readlane.  No LDS and no barrier is needed and each row is gathered once.
 //  * Boundary nodes gather the populations of the interior node they
 //    extrapolate from instead of their own (non-equilibrium extrapolation),
 //    so the wavefront's loads stay uniform; the rebuild is a short divergent
@@ -46,6 +47,10 @@ constexpr int kWave = 64;
 constexpr int kTile = 64;  // owned columns per wavefront (aligned)
 constexpr int kBlock = 256;
 constexpr int kWavesPerBlock = kBlock / kWave;
+constexpr int kHaloRows = kWave / 2;  // rows served by one halo gather (one per lane half)
+// wavefronts per block of the single-grid step, marching in lockstep
+// (measured best on 8192^2: 8 for FP32 storage, 4 for the 16-bit codecs)
+template <int ST> constexpr int kLock = ST == LB_STORE_F32 ? 8 : 4;
 constexpr int kRedBlocks = 1024;
 constexpr int kNred = 8;
 constexpr int kPlanePadBytes = 4096;  // appended to each plane: spreads the 18 streams over HBM channels
@@ -125,6 +130,9 @@ __device__ __forceinline__ Planes planes(const char *base, long long pb) {
     return P;
 }
 
+typedef _Float16 H2 __attribute__((ext_vector_type(2)));
+typedef __bf16 B2 __attribute__((ext_vector_type(2)));
+
 // q is the plane (0..17); after unrolling it is a compile-time constant.
 template <int ST> struct Codec;
 template <> struct Codec<LB_STORE_F32> {
@@ -153,16 +161,17 @@ template <> struct Codec<LB_STORE_F16> {
         const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, (q % 9) * P.pb, 0);
         return (float)__builtin_bit_cast(_Float16, b) * (1.f / f16_scale(q));
     }
-    // rb: random bits; the 13 float mantissa bits below the FP16 mantissa are
-    // rounded stochastically (add, then truncate), which leaves no systematic
-    // rounding bias in steady flows.  rb = 0 gives round-toward-zero of those
-    // bits followed by an exact conversion.
+    // rb: random bits; the conversion rounds stochastically (gfx950's
+    // v_cvt_sr_f16_f32 adds the high bits of rb below the kept mantissa of the
+    // magnitude, then truncates), which leaves no systematic rounding bias in
+    // steady flows.
     static __device__ __forceinline__ void st(const Planes &P, unsigned vo, float v, int q, unsigned rb) {
         const Rsrc r = q < 9 ? P.f : P.h;
-        unsigned u = __float_as_uint(v * f16_scale(q));
-        u = (u + (rb >> 19)) & ~0x1FFFu;
-        const _Float16 h = (_Float16)__uint_as_float(u);
-        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h), r, vo, (q % 9) * P.pb, kNT);
+        // the conversion writes one half of a register; the other half is
+        // never stored, so the input's own register serves as the old value
+        const float sv = v * f16_scale(q);
+        const H2 h = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(H2, sv), sv, rb, false);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), r, vo, (q % 9) * P.pb, kNT);
     }
 };
 template <> struct Codec<LB_STORE_BF16> {
@@ -175,9 +184,8 @@ template <> struct Codec<LB_STORE_BF16> {
     // stochastic rounding of the 16 dropped mantissa bits (see the FP16 codec)
     static __device__ __forceinline__ void st(const Planes &P, unsigned vo, float v, int q, unsigned rb) {
         const Rsrc r = q < 9 ? P.f : P.h;
-        unsigned u = __float_as_uint(v);
-        u += rb >> 16;
-        __builtin_amdgcn_raw_buffer_store_b16((unsigned short)(u >> 16), r, vo, (q % 9) * P.pb, kNT);
+        const B2 h = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(B2, v), v, rb, false);
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), r, vo, (q % 9) * P.pb, kNT);
     }
 };
 
@@ -562,7 +570,8 @@ __device__ __forceinline__ void collide(const KArgs &a, const float d[18], const
 
 // Counter-based random bits for the stochastic rounding of the 16-bit codecs:
 // a 32-bit integer hash (two multiply-xorshift rounds) of the node's linear
-// index and the time step, spread over the 18 planes by odd multipliers.
+// index and the time step, rotated by a different amount for each of the 18
+// planes so that each plane's rounding reads a different window of it.
 __device__ __forceinline__ unsigned hash32(unsigned x) {
     x ^= x >> 16;
     x *= 0x7feb352du;
@@ -571,7 +580,9 @@ __device__ __forceinline__ unsigned hash32(unsigned x) {
     x ^= x >> 16;
     return x;
 }
-__device__ __forceinline__ unsigned plane_bits(unsigned h, int q) { return h * (0x9E3779B1u + 2u * (unsigned)q); }
+__device__ __forceinline__ unsigned plane_bits(unsigned h, int q) {
+    return __builtin_amdgcn_alignbit(h, h, (7u * (unsigned)q) & 31u);
+}
 
 __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
     const int xcd = b & 7, idx = b >> 3, per = nb >> 3, rem = nb & 7;
@@ -632,21 +643,6 @@ __device__ __forceinline__ void collide_store(const KArgs &a, const Planes &D, c
     }
 }
 
-// x-component of Q at the two columns just outside the wavefront's tile for
-// row y: lane 0 computes column x0 - 1, lane 1 column x0 + 64 (the other lanes
-// repeat a valid node and are ignored); the values are broadcast to the wave.
-template <int ST, bool BC, class F>
-__device__ __forceinline__ void halo_q(const KArgs &a, const Planes &S, int hxw, bool hxin, int y, float &qhl,
-                                       float &qhr) {
-    float dh[18];
-    Mom mh;
-    float qx, qy;
-    row_issue<ST, BC>(a, S, hxw, y, dh);
-    row_finish<ST, BC, F>(a, S, hxw, hxin, y, dh, mh, qx, qy);
-    qhl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qx), 0));
-    qhr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qx), 1));
-}
-
 // lane's column x of a tile, wrapped (periodic) or clamped (bounded); xin
 // tells whether x lies inside the domain.
 __device__ __forceinline__ int col_wrap(const KArgs &a, int x, bool &xin) {
@@ -659,16 +655,51 @@ __device__ __forceinline__ int col_wrap(const KArgs &a, int x, bool &xin) {
     return min(max(x, 0), a.nx - 1);
 }
 
-// One wavefront's strip: 64 aligned columns from x0 = 64 tx, rows
-// [R sy, R sy + R).  Shared by the single-grid and the packed (serving) step.
+// x-component of Q (Eq. 48) at the two columns just outside the wavefront's
+// tile for up to 32 rows from yb: lanes 0..31 take column x0 - 1, lanes
+// 32..63 column x0 + 64, row yb + (lane & 31); lanes past the strip's last row
+// repeat that row and go unused, and a side that is not needed is skipped.
+// One wide gather thus serves 32 rows; the row loop picks its values out
+// with readlane.
 template <int ST, bool BC, class F>
+__device__ __forceinline__ float halo_chunk(const KArgs &a, const Planes &S, int x0, int lane, int yb, int ylast,
+                                            bool need_l, bool need_r) {
+    const bool left = lane < kHaloRows;
+    float qx = 0.f;
+    if (left ? need_l : need_r) {
+        bool hxin;
+        const int hxw = col_wrap(a, left ? x0 - 1 : x0 + kTile, hxin);
+        const int hy = min(yb + (lane & (kHaloRows - 1)), ylast);
+        float dh[18];
+        Mom mh;
+        float qy;
+        row_issue<ST, BC>(a, S, hxw, hy, dh);
+        row_finish<ST, BC, F>(a, S, hxw, hxin, hy, dh, mh, qx, qy);
+    }
+    return qx;
+}
+
+// One strip: LW wavefronts side by side, wavefront w owning the 64 aligned
+// columns from x0 = 64 tx (tx = its tile), all of them marching up rows
+// [R sy, R sy + R) in step.  With LW > 1 the block's wavefronts are adjacent
+// tiles: each row they meet at one barrier and pass the Q_x of their edge
+// lanes to their neighbours through LDS, so only the two outer wavefronts
+// gather halo columns, and the cache lines that neighbouring tiles share are
+// fetched by both at the same time.  LW = 1 is the packed (serving) step,
+// where every wavefront runs on its own.
+template <int ST, bool BC, class F, int LW>
 __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict__ src, char *__restrict__ dst,
                                           int tx, int sy, unsigned step) {
+    // Q_x of the edge lanes (0: lane 0, 1: lane 63) of each wavefront, three
+    // row slots so that one barrier per row separates writes from reads
+    __shared__ float qedge[3][LW][2];
     const int lane = threadIdx.x & (kWave - 1);
+    const int w = LW > 1 ? (int)(threadIdx.x >> 6) : 0;
+    const bool edge_l = w == 0, edge_r = w == LW - 1;
+    const int wl = max(w - 1, 0), wr = min(w + 1, LW - 1);
     const int x0 = tx * kTile, gx = x0 + lane;
-    bool xin, hxin;
+    bool xin;
     const int xw = col_wrap(a, gx, xin);
-    const int hxw = col_wrap(a, lane == 0 ? x0 - 1 : (lane == 1 ? x0 + kTile : gx), hxin);
     const bool owned = gx < a.nx;
     const int y0 = sy * a.strip_rows;
     const int y1 = min(y0 + a.strip_rows, a.ny);
@@ -676,42 +707,70 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
     const unsigned eb = Codec<ST>::bytes, pitch_b = (unsigned)a.pitch * eb;
     unsigned vo = ((unsigned)y0 * a.pitch + xw) * eb;
 
+    // halo Q_x from the gathered chunk (outer wavefronts only)
+    float qh = 0.f;
+    if (edge_l || edge_r) qh = halo_chunk<ST, BC, F>(a, S, x0, lane, y0, y1 - 1, edge_l, edge_r);
+
     // two row states used alternately (the loop is unrolled by two)
     float dA[18], dB[18];
     Mom mA, mB;
-    float qyp, qxA, qyA, qxB, qyB, qhl, qhr;
+    float qyp, qxA, qyA, qxB, qyB;
     row_issue<ST, BC>(a, S, xw, y0 - 1, dA);
     row_finish<ST, BC, F>(a, S, xw, xin, y0 - 1, dA, mA, qxA, qyp);
     row_issue<ST, BC>(a, S, xw, y0, dA);
     int kA = row_finish<ST, BC, F>(a, S, xw, xin, y0, dA, mA, qxA, qyA), kB;
+    int sc = 0;  // LDS slot of the current row
+    if (LW > 1) {
+        if (lane == 0) qedge[0][w][0] = qxA;
+        if (lane == kWave - 1) qedge[0][w][1] = qxA;
+    }
+
+    // One row: issue the look-ahead row's loads, finish it, publish its edge
+    // Q_x, then collide and store the current row.
+    auto row = [&](int y, float(&dC)[18], const Mom &mC, int kC, float qxC, float(&dN)[18], Mom &mN, int &kN,
+                   float &qxN, float &qyN) {
+        row_issue<ST, BC>(a, S, xw, y + 1, dN);
+        const int k = y - y0, r = k & (kHaloRows - 1);
+        if ((edge_l || edge_r) && r == 0 && k != 0)
+            qh = halo_chunk<ST, BC, F>(a, S, x0, lane, y, y1 - 1, edge_l, edge_r);
+        float qhl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qh), r));
+        float qhr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qh), kHaloRows + r));
+        kN = row_finish<ST, BC, F>(a, S, xw, xin, y + 1, dN, mN, qxN, qyN);
+        if (LW > 1) {
+            const int sn = sc == 2 ? 0 : sc + 1;
+            if (lane == 0) qedge[sn][w][0] = qxN;
+            if (lane == kWave - 1) qedge[sn][w][1] = qxN;
+            __syncthreads();
+            if (!edge_l) qhl = qedge[sc][wl][1];
+            if (!edge_r) qhr = qedge[sc][wr][0];
+            sc = sn;
+        }
+        collide_store<ST, BC, F>(a, D, dC, mC, kC, lane, qxC, qhl, qhr, qyp, qyN, owned, vo, step);
+        vo += pitch_b;
+    };
     int y = y0;
     for (;;) {
         if (y >= y1) break;
-        row_issue<ST, BC>(a, S, xw, y + 1, dB);
-        halo_q<ST, BC, F>(a, S, hxw, hxin, y, qhl, qhr);
-        kB = row_finish<ST, BC, F>(a, S, xw, xin, y + 1, dB, mB, qxB, qyB);
-        collide_store<ST, BC, F>(a, D, dA, mA, kA, lane, qxA, qhl, qhr, qyp, qyB, owned, vo, step);
+        row(y, dA, mA, kA, qxA, dB, mB, kB, qxB, qyB);
         qyp = qyA;
         ++y;
-        vo += pitch_b;
         if (y >= y1) break;
-        row_issue<ST, BC>(a, S, xw, y + 1, dA);
-        halo_q<ST, BC, F>(a, S, hxw, hxin, y, qhl, qhr);
-        kA = row_finish<ST, BC, F>(a, S, xw, xin, y + 1, dA, mA, qxA, qyA);
-        collide_store<ST, BC, F>(a, D, dB, mB, kB, lane, qxB, qhl, qhr, qyp, qyA, owned, vo, step);
+        row(y, dB, mB, kB, qxB, dA, mA, kA, qxA, qyA);
         qyp = qyB;
         ++y;
-        vo += pitch_b;
     }
 }
 
 // ----------------------------------------------------------------- kernels
+// Block = kLock wavefronts on adjacent tiles of one strip (see run_strip).
 template <int ST, bool BC, class F>
-__global__ __launch_bounds__(kBlock) void k_step(const KArgs a, const char *__restrict__ src, char *__restrict__ dst) {
+__global__ __launch_bounds__(kWave * kLock<ST>) void k_step(const KArgs a, const char *__restrict__ src,
+                                                            char *__restrict__ dst) {
+    constexpr int LW = kLock<ST>;
     const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
-    const int wv = blk * kWavesPerBlock + (threadIdx.x >> 6);
-    if (wv >= a.tiles_x * a.n_strips) return;
-    run_strip<ST, BC, F>(a, src, dst, wv % a.tiles_x, wv / a.tiles_x, a.step);
+    const int bxs = (a.tiles_x + LW - 1) / LW;
+    const int bx = blk % bxs, sy = blk / bxs;
+    run_strip<ST, BC, F, LW>(a, src, dst, bx * LW + (int)(threadIdx.x >> 6), sy, a.step);
 }
 
 // Packed step of many grids (serving): the work list holds one item per
@@ -733,12 +792,16 @@ __global__ __launch_bounds__(kBlock) void k_step_multi(const SlotDev *__restrict
                                                        int i) {
     const int nw = *nitems;
     const int waves = gridDim.x * kWavesPerBlock;
-    for (int w = blockIdx.x * kWavesPerBlock + (threadIdx.x >> 6); w < nw; w += waves) {
+    // the item index is the same on every lane of the wavefront: readfirstlane
+    // lets the compiler load the item and its grid's arguments with scalar
+    // loads into SGPRs instead of once per lane into VGPRs
+    const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
+    for (int w = w0; w < nw; w += waves) {
         const WorkItem it = items[w];
         const SlotDev &sd = slots[it.slot];
         const int c = (sd.cur + i) & 1;
-        run_strip<ST, true, Dyn>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]), it.tx, it.sy,
-                                 (unsigned)(sd.n + i));
+        run_strip<ST, true, Dyn, 1>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]), it.tx, it.sy,
+                                    (unsigned)(sd.n + i));
     }
 }
 
@@ -1020,9 +1083,9 @@ void set_strip(lb_handle *h) {
     a.tiles_x = (a.nx + kTile - 1) / kTile;
     int R = h->strip_user;
     if (R <= 0) {
-        // 16-row strips (measured best on 4096^2 and 8192^2); shorter ones when
-        // the grid would not give 256 CUs enough wavefronts
-        R = 16;
+        // 8-row strips (measured best on 8192^2); shorter ones when the grid
+        // would not give 256 CUs enough wavefronts
+        R = 8;
         while (R > 4 && (long long)a.tiles_x * ((a.ny + R - 1) / R) < 16384) R >>= 1;
     }
     a.strip_rows = R;
@@ -1103,9 +1166,9 @@ void set_inlet(lb_handle *h, long n) {
 template <int ST, bool BC, class F>
 void launch_step(lb_handle *h) {
     const KArgs &a = h->a;
-    const long long waves = (long long)a.tiles_x * a.n_strips;
-    const int blocks = (int)((waves + kWavesPerBlock - 1) / kWavesPerBlock);
-    hipLaunchKernelGGL((k_step<ST, BC, F>), dim3(blocks), dim3(kBlock), 0, h->stream, a, h->pops[h->cur],
+    constexpr int LW = kLock<ST>;
+    const int blocks = (a.tiles_x + LW - 1) / LW * a.n_strips;
+    hipLaunchKernelGGL((k_step<ST, BC, F>), dim3(blocks), dim3(kWave * LW), 0, h->stream, a, h->pops[h->cur],
                        h->pops[1 - h->cur]);
 }
 

@@ -94,6 +94,11 @@ def load():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        # torch ships its own HIP runtime under the same soname as the system
+        # one.  Importing torch first makes the library bind to that runtime,
+        # so device pointers and streams from torch are valid in both; loaded
+        # the other way round the process would hold two runtimes.
+        import torch  # noqa: F401
         lib = C.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(lib, name)

@@ -1,11 +1,11 @@
-"""Continuous-batching server (lbs_*): results equal the single-grid path and
-are the same alone and in a mix; admission follows the pool's byte budget;
+"""Continuous-batching server (lbs_*): results agree with the single-grid path
+to the FP32 tolerance and are bit-identical alone and in a mix; admission follows the pool's byte budget;
 a diverging request is retired without disturbing the others."""
 import numpy as np
 import pytest
 
 from paper_1109_6672_amd import lbddf, workloads as W
-from tests.gpu_common import rel_errors
+from tests.gpu_common import TOL, rel_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -45,8 +45,11 @@ def test_server_matches_single_grid(gpu):
         assert st["state"] == "step_cap" and st["steps"] == 600, st
         s = lbddf.Solver(p).init(*_fields(p, k)).step(600)
         e = rel_errors(srv.result(rid), s.macros())
-        print(f"[case] server vs single grid {p['nx']}x{p['ny']}: {e}")
-        assert max(e) < 1e-6
+        print(f"[case] server vs single grid {p['nx']}x{p['ny']}: {e}", flush=True)
+        # same arithmetic in two separately compiled kernels (the packed one runs
+        # each wavefront on its own, the single-grid one in lockstep blocks):
+        # fused multiply-adds may be formed differently, so the last bits differ
+        assert max(e) < TOL["f32"]
 
 
 def test_alone_and_in_the_mix_are_identical(gpu):
