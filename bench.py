@@ -27,8 +27,12 @@ BYTES_PER_NODE = {"f32": 144, "f16": 72, "bf16": 72}  # 18 loads + 18 stores per
 
 
 def kernel_source_hash() -> str:
+    """Hash of the device code (everything above the host-side section of
+    lbddf.hip): a profile stays valid while the kernels are unchanged."""
     with open(os.path.join(ROOT, "paper_1109_6672_amd", "csrc", "lbddf.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+        src = fh.read()
+    cut = src.find(b"// ------------------------------------------------------------- host side")
+    return hashlib.sha256(src if cut < 0 else src[:cut]).hexdigest()[:16]
 
 
 def measured_traffic(key: str, nodes: int):
@@ -101,21 +105,22 @@ def cpu_baseline(seconds: float):
                 sample=f"periodic {n}x{n}, same recipe, {steps} steps in {t:.1f} s (FP64, OpenMP over rows)")
 
 
-def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 200):
+def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 200, tol: float = 1e-8,
+                    cap: int = 100_000):
     """The continuous-batching server against one solve per launch, on the
     same seeded stream of cavity requests (Poisson arrivals, 50 per second)."""
     from paper_1109_6672_amd import lbddf, serving as SV, workloads as W
 
     reqs = W.serving_mix(n_requests, sizes=sizes, rate=50.0)
     pool = lbddf.load().lbs_pool_overhead() + sum(lbddf.state_bytes(r["params"]) + 256 for r in reqs)
-    packed, srv, _ = SV.run_server(reqs, pool, k_steps=k_steps, tol=1e-6, max_steps=20000)
+    packed, srv, _ = SV.run_server(reqs, pool, k_steps=k_steps, tol=tol, max_steps=cap)
     srv.close()
-    seq = SV.run_sequential(reqs, k_steps=k_steps, tol=1e-6, max_steps=20000)
+    seq = SV.run_sequential(reqs, k_steps=k_steps, tol=tol, max_steps=cap)
     keep = ("p50_s", "p99_s", "solves_per_s", "mlups", "wall_s", "states")
     return {
         "workload": f"{n_requests} differentially heated cavity requests, edges {'/'.join(map(str, sizes))}, "
                     "Poisson arrivals 50/s, Ra log-uniform 1e3..1e6, dT/T0 uniform 0.02..1.2, FP32, "
-                    f"residual checked every {k_steps} steps, tol 1e-6, cap 20000 steps",
+                    f"residual checked every {k_steps} steps, tol {tol:g}, plateau test, cap {cap} steps",
         "packed": {k: packed[k] for k in keep},
         "one_at_a_time": {k: seq[k] for k in keep},
         "solves_per_s_ratio": packed["solves_per_s"] / seq["solves_per_s"],

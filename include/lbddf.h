@@ -180,10 +180,13 @@ const char *lb_last_error(void);
  * resident grids) become free.  One lbs_advance call runs k steps of every
  * resident grid as a hipGraph of k launches of one packed kernel (the same
  * per-node step as lb_step), then reads every grid's FP64 convergence
- * residual r = ||T - T_snap|| / ||T|| (snapshot k steps earlier) in one copy,
- * retires grids that converged (r < tol), reached a plateau (no new minimum
- * over 10 checks), hit max_steps or became unstable, stores their final
- * fields on the host, frees their memory and admits waiting requests.
+ * residual r = ||T - T_snap|| / ||T|| (snapshot k steps earlier; the first
+ * at admission) in one copy,
+ * retires grids that converged (r < tol), reached a plateau (r below 1e-3 of
+ * its largest value and no new minimum for max(10, n/2) of its n checks so
+ * far, minima counted from that maximum), hit max_steps or became unstable,
+ * stores their final fields on the host, frees their memory and admits
+ * waiting requests.
  * Requests of one server share its storage type; inlet sides are not served.
  * One server must not be used by two threads at once.
  * ------------------------------------------------------------------------ */

@@ -36,8 +36,12 @@
  *   - the walls use non-equilibrium extrapolation from the nearest interior
  *     node along the inward normal (the diagonal neighbour at corners):
  *     pop_b = eq(rho_b,u_b,T_b) + [pop_f - eq(rho_f,u_f,T_f)] for f^ and h-;
- *   - a Dirichlet-temperature wall takes rho_b = rho_f T_f / T_b (pressure
- *     extrapolation) unless density extrapolation is asked for (rho_b = rho_f);
+ *   - a Dirichlet-temperature wall takes its density from pressure
+ *     extrapolation that respects the hydrostatic balance of the body force,
+ *     p_b = p_f exp(g (y_f - y_b) / (R (T_f + T_b)/2)) with p = rho R T (so
+ *     rho_b = rho_f T_f / T_b without gravity), unless density extrapolation
+ *     is asked for (rho_b = rho_f); plain p_b = p_f lets a closed box at rest
+ *     under gravity leak mass through its horizontal walls every step;
  *   - an adiabatic wall takes the second-order one-sided zero-gradient value
  *     T_b = (4 T_1 - T_2)/3 from the first two nodes along the inward normal
  *     (the diagonal at corners), and rho_b as for a Dirichlet wall;
@@ -358,6 +362,14 @@ static void inlet_values(const orc_grid *g, double *rho, double *ux, double *uy,
     *T = p->T0 * (1.0 + (gamma - 1.0) * U0 * s / cs);
 }
 
+/* Wall density from pressure extrapolation that keeps the hydrostatic
+ * balance of the body force a = (0, -rho g): p_b = p_f exp(g dy / (R T_m))
+ * with dy = y_f - y_b and T_m = (T_f + T_b)/2, p = rho R T. */
+static double wall_density(const orc_grid *g, double rf, double Tf, double Tb, int dy) {
+    const double Tm = 0.5 * (Tf + Tb);
+    return rf * Tf / Tb * exp(g->p.g * (double)dy / (g->p.R * Tm));
+}
+
 /* Boundary treatment (see the header for the readings). Reads only interior
  * nodes' populations and moments (an axis with an adiabatic wall has at least
  * four nodes, so the second node along the normal is interior too), writes
@@ -412,14 +424,14 @@ static void stage_boundary(orc_grid *g) {
                 }
                 if (dirichlet) {
                     Tb = Twall;
-                    rb = (g->p.rho_extrap == ORC_RHO_PRESSURE) ? rf * Tf / Tb : rf;
+                    rb = (g->p.rho_extrap == ORC_RHO_PRESSURE) ? wall_density(g, rf, Tf, Tb, fj - j) : rf;
                 } else {
                     /* adiabatic: second-order one-sided zero normal gradient,
                      * T_b = (4 T_1 - T_2)/3 along the inward normal */
                     const int di = fi - i, dj = fj - j;
                     const double T2 = g->T[nid(g, fi + di, fj + dj)];
                     Tb = (4.0 * Tf - T2) / 3.0;
-                    rb = (g->p.rho_extrap == ORC_RHO_PRESSURE) ? rf * Tf / Tb : rf;
+                    rb = (g->p.rho_extrap == ORC_RHO_PRESSURE) ? wall_density(g, rf, Tf, Tb, fj - j) : rf;
                 }
                 double feb[NQ], heb[NQ], fef[NQ], hef[NQ];
                 feq(g, rb, uxb, uyb, Tb, feb);

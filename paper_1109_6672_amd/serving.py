@@ -18,6 +18,28 @@ def _summary(lat, node_updates, wall, states):
                 states={s: states.count(s) for s in set(states)})
 
 
+class Plateau:
+    """The server's plateau test (lbs_advance): the residual lies below 1e-3
+    of its largest value so far and has made no new minimum for max(10, n/2)
+    of the n checks so far, minima counted from that maximum."""
+
+    def __init__(self):
+        self.peak, self.best, self.stall, self.checks = 0.0, np.inf, 0, 0
+
+    def update(self, r: float) -> bool:
+        self.checks += 1
+        if r > self.peak:
+            self.peak = self.best = r
+            self.stall = 0
+        elif r < self.best:
+            self.best, self.stall = r, 0
+        else:
+            self.stall += 1
+            if self.stall >= max(10, self.checks // 2) and r < 1e-3 * self.peak:
+                return True
+        return False
+
+
 def run_server(requests, pool_bytes, storage="f32", k_steps=200, tol=1e-6, max_steps=20000, realtime=True):
     """Drives a Server with the requests' arrival times (seconds from start)."""
     srv = lbddf.Server(pool_bytes, storage=storage, k_steps=k_steps)
@@ -59,7 +81,7 @@ def run_sequential(requests, storage="f32", k_steps=200, tol=1e-6, max_steps=200
         f = r.get("fields")
         s.init(*(f if f is not None else (None,) * 4))
         s.residual(update=True)
-        best, stall, state = np.inf, 0, "step_cap"
+        pl, state = Plateau(), "step_cap"
         while s.time < max_steps:
             s.step(k_steps)
             d = s.diag(check=False)
@@ -70,13 +92,9 @@ def run_sequential(requests, storage="f32", k_steps=200, tol=1e-6, max_steps=200
             if res < tol:
                 state = "converged"
                 break
-            if res < best:
-                best, stall = res, 0
-            else:
-                stall += 1
-                if stall >= 10:
-                    state = "plateau"
-                    break
+            if pl.update(res):
+                state = "plateau"
+                break
         s.macros()
         done = time.perf_counter() - t0
         lat.append(done - (r["t"] if realtime else 0.0))

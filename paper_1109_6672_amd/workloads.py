@@ -255,7 +255,8 @@ def serving_mix(n_requests: int, sizes=(64, 128, 256, 512, 1024), Ra_range=(1e3,
     `sizes`), Ra (log-uniform) and dT/T0 (uniform).  The viscosity is chosen
     so that the buoyancy velocity nu sqrt(Ra / Pr) / H equals `u_target`,
     with tau_f(T_r) = 3 nu + 1/2 kept >= tau_min (requests at that bound are
-    flagged "under_resolved"); large dT uses the Sutherland law.  Returns a
+    flagged "under_resolved"); large dT (> 0.2) uses the Sutherland law and
+    energy-mode rates s_e = s_zeta = 1.5.  Returns a
     list of dicts with keys t (arrival, s), params, n, Ra, dT, flags.
     """
     u = uniform01(SEED_BASE + k, 4 * n_requests).reshape(n_requests, 4)
@@ -272,5 +273,10 @@ def serving_mix(n_requests: int, sizes=(64, 128, 256, 512, 1024), Ra_range=(1e3,
             nu = (tau_min - 0.5) / 3
             flags.append("under_resolved")
         p = cavity(n, Ra, dT, nu, Pr=Pr, sutherland=dT > 0.2, storage=storage)
+        if dT > 0.2:
+            # large dT: energy-mode rates untied from tau_f (allowed for
+            # low-Mach flows, Sec. III), as the tied form diverges at the
+            # cold bottom corner on fine grids
+            p.update(s_e=1.5, s_zeta=1.5)
         out.append(dict(t=t, params=p, n=n, Ra=Ra, dT=dT, flags=flags))
     return out

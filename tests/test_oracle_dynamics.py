@@ -262,6 +262,31 @@ def test_cavity_walls_and_corners():
     np.testing.assert_allclose(rho[1:-1, 0] * T[1:-1, 0], rho[1:-1, 1] * T[1:-1, 1], rtol=1e-15)
 
 
+def test_closed_box_under_gravity_keeps_its_mass_and_comes_to_rest():
+    """Isothermal closed box with a body force a = (0, -rho g): the exact
+    solution is hydrostatic rest, p ~ exp(-g y / (R T0)).  The walls must be
+    impermeable in that state: after the start-up transient the mass stays
+    constant (with p_b = p_f at the horizontal walls it falls by about 1e-5
+    per step here), the residual currents are small and the density profile
+    is the hydrostatic one."""
+    n, g = 32, 2e-3
+    p = W.cavity(n, 1e4, 0.2, 0.05)
+    p["sides"] = [dict(sd, T=1.0) for sd in p["sides"]]
+    p["g"] = g
+    rho0, ux0, uy0, T0 = W.rest_fields(p)
+    rho0 = rho0 * np.exp(-3 * g * np.arange(n))[:, None]  # start near the hydrostatic state
+    o = O.Oracle(p).init(rho0, ux0, uy0, T0)
+    o.step(10000)
+    m1 = o.diag()["mass"]
+    o.step(4000)
+    m2 = o.diag()["mass"]
+    rho, ux, uy, T = o.macros()
+    assert abs(m2 / m1 - 1) < 1e-8, (m1, m2)  # p_b = p_f: -4.5e-2 over the same steps
+    assert np.max(np.hypot(ux, uy)) < 2e-5
+    ratio = rho[1:, n // 2] / rho[:-1, n // 2]
+    np.testing.assert_allclose(ratio, math.exp(-3 * g), rtol=2e-5)
+
+
 def test_applied_correction_meets_eq28_on_the_grid():
     """One step with and without the correction term from the same state: the
     difference of the post-collision f is (1 - s/2) C with C of Eq. 49, whose
