@@ -64,6 +64,32 @@ def test_small_dT_cavity_reproduces_table_ii():
         assert abs(m[k] - row[k]) < 0.02, (k, m[k], row[k])
 
 
+def test_small_dT_cavity_converged_state_against_the_oracle():
+    """Config 2 run 268,000 steps (its convergence above) on the GPU and in the
+    FP64 oracle.  rho and T meet the FP32 bar and the Table II quantities agree
+    to 1e-3; the velocity does not meet 1e-5: the flow's velocity (about
+    3.5e-3) is driven by a buoyancy 50 times smaller than the hydrostatic
+    forces (dT/T0 = 0.02), and FP32 rounding accumulates over the viscous
+    time H^2/nu of some 8e5 steps (measured: 5e-4)."""
+    from oracle import oracle as O
+
+    p = W.cavity(128, 1e4, 0.02, 0.02)
+    f = W.noisy_temperature_fields(p)
+    print("[case] Table II Ra=1e4 cavity 128x128, 268000 steps, GPU and oracle", flush=True)
+    g = lbddf.Solver(p).init(*f).step(268_000).macros()
+    r = O.Oracle(p).init(*f).step(268_000).macros()
+    e = rel_errors(g, r)
+    mg, mr = P.cavity_metrics(p, *g[1:]), P.cavity_metrics(p, *r[1:])
+    print(f"       rel err rho {e[0]:.3e} u {e[1]:.3e} T {e[2]:.3e}; Nu {mg['Nu']:.5f} / {mr['Nu']:.5f}, "
+          f"u_max {mg['u_max']:.4f} / {mr['u_max']:.4f}, v_max {mg['v_max']:.4f} / {mr['v_max']:.4f}", flush=True)
+    assert e[0] < 2e-5 and e[2] < 2e-5, e
+    for k in ("Nu", "u_max", "v_max"):
+        assert abs(mg[k] / mr[k] - 1) < 1e-3, (k, mg[k], mr[k])
+    assert mg["y_max"] == mr["y_max"] and mg["x_max"] == mr["x_max"]
+    if max(e) > TOL["f32"]:
+        pytest.xfail(f"FP32 misses 1e-5 on the converged gravity-driven flow: errors {e}")
+
+
 def _beta_eq56(mu, Pr, b, period):
     """Spatial attenuation rate of Eq. 56 for a source of frequency 1/period
     (lattice units, rho0 = 1, R T0 = 1/3)."""
@@ -140,6 +166,8 @@ def test_large_dT_cavity_downscale_against_the_oracle(large_dT_reference, storag
           f"T {e[2]:.3e}", flush=True)
     if storage == "f32":
         assert e[2] < 2e-5 and max(e) < 5e-5, e
+        if max(e) > TOL["f32"]:
+            pytest.xfail(f"FP32 error grows with the wall mass drift of this proxy: errors {e}")
         return
     if max(e) > TOL[storage]:
         pytest.xfail(f"{storage} storage misses 2e-3 on O(1) deviations from rest: errors {e}")
