@@ -665,20 +665,20 @@ __device__ __forceinline__ int col_wrap(const KArgs &a, int x, bool &xin) {
 }
 
 // x-component of Q (Eq. 48) at the two columns just outside the wavefront's
-// tile for up to 32 rows from yb: lanes 0..31 take column x0 - 1, lanes
-// 32..63 column x0 + 64, row yb + (lane & 31); lanes past the strip's last row
-// repeat that row and go unused, and a side that is not needed is skipped.
-// One wide gather thus serves 32 rows; the row loop picks its values out
-// with readlane.
+// tile for up to 32 rows of the strip's march from row yb (direction dir):
+// lanes 0..31 take column x0 - 1, lanes 32..63 column x0 + 64, row
+// yb + dir (lane & 31); lanes past the strip's end repeat its last row and go
+// unused, and a side that is not needed is skipped.  One wide gather thus
+// serves 32 rows; the row loop picks its values out with readlane.
 template <int ST, bool BC, class F>
-__device__ __forceinline__ float halo_chunk(const KArgs &a, const Planes &S, int x0, int lane, int yb, int ylast,
-                                            bool need_l, bool need_r) {
+__device__ __forceinline__ float halo_chunk(const KArgs &a, const Planes &S, int x0, int lane, int yb, int dir,
+                                            int ylo, int yhi, bool need_l, bool need_r) {
     const bool left = lane < kHaloRows;
     float qx = 0.f;
     if (left ? need_l : need_r) {
         bool hxin;
         const int hxw = col_wrap(a, left ? x0 - 1 : x0 + kTile, hxin);
-        const int hy = min(yb + (lane & (kHaloRows - 1)), ylast);
+        const int hy = min(max(yb + dir * (lane & (kHaloRows - 1)), ylo), yhi);
         float dh[18];
         Mom mh;
         float qy;
@@ -689,13 +689,16 @@ __device__ __forceinline__ float halo_chunk(const KArgs &a, const Planes &S, int
 }
 
 // One strip: LW wavefronts side by side, wavefront w owning the 64 aligned
-// columns from x0 = 64 tx (tx = its tile), all of them marching up rows
-// [R sy, R sy + R) in step.  With LW > 1 the block's wavefronts are adjacent
-// tiles: each row they meet at one barrier and pass the Q_x of their edge
-// lanes to their neighbours through LDS, so only the two outer wavefronts
-// gather halo columns, and the cache lines that neighbouring tiles share are
-// fetched by both at the same time.  LW = 1 is the packed (serving) step,
-// where every wavefront runs on its own.
+// columns from x0 = 64 tx (tx = its tile), all of them marching through rows
+// [R sy, R sy + R) in step: up on even strips, down on odd ones, so that two
+// neighbouring strips reach the rows they share (each reads two rows of the
+// other) at the same moment, both at their start or both at their end, while
+// those rows are still in L2.  With LW > 1 the block's wavefronts are
+// adjacent tiles: each row they meet at one barrier and pass the Q_x of their
+// edge lanes to their neighbours through LDS, so only the two outer
+// wavefronts gather halo columns, and the cache lines that neighbouring tiles
+// share are fetched by both at the same time.  LW = 1 is the packed (serving)
+// step, where every wavefront runs on its own.
 template <int ST, bool BC, class F, int LW>
 __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict__ src, char *__restrict__ dst,
                                           int tx, int sy, unsigned step) {
@@ -712,39 +715,44 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
     const bool owned = gx < a.nx;
     const int y0 = sy * a.strip_rows;
     const int y1 = min(y0 + a.strip_rows, a.ny);
+    const int dir = (sy & 1) ? -1 : 1;
+    const int ys = dir > 0 ? y0 : y1 - 1;  // first row of the march
     const Planes S = planes(src, a.plane_bytes), D = planes(dst, a.plane_bytes);
-    const unsigned eb = Codec<ST>::bytes, pitch_b = (unsigned)a.pitch * eb;
-    unsigned vo = ((unsigned)y0 * a.pitch + xw) * eb;
+    const unsigned eb = Codec<ST>::bytes;
+    const unsigned dvo = (unsigned)(dir * a.pitch) * eb;  // store offset step (wraps for dir < 0)
+    unsigned vo = ((unsigned)ys * a.pitch + xw) * eb;
 
     // halo Q_x from the gathered chunk (outer wavefronts only)
     float qh = 0.f;
-    if (edge_l || edge_r) qh = halo_chunk<ST, BC, F>(a, S, x0, lane, y0, y1 - 1, edge_l, edge_r);
+    if (edge_l || edge_r) qh = halo_chunk<ST, BC, F>(a, S, x0, lane, ys, dir, y0, y1 - 1, edge_l, edge_r);
 
-    // two row states used alternately (the loop is unrolled by two)
+    // two row states used alternately (the loop is unrolled by two); qyb is
+    // Q_y of the row behind the current one
     float dA[18], dB[18];
     Mom mA, mB;
-    float qyp, qxA, qyA, qxB, qyB;
-    row_issue<ST, BC>(a, S, xw, y0 - 1, dA);
-    row_finish<ST, BC, F>(a, S, xw, xin, y0 - 1, dA, mA, qxA, qyp);
-    row_issue<ST, BC>(a, S, xw, y0, dA);
-    int kA = row_finish<ST, BC, F>(a, S, xw, xin, y0, dA, mA, qxA, qyA), kB;
+    float qyb, qxA, qyA, qxB, qyB;
+    row_issue<ST, BC>(a, S, xw, ys - dir, dA);
+    row_finish<ST, BC, F>(a, S, xw, xin, ys - dir, dA, mA, qxA, qyb);
+    row_issue<ST, BC>(a, S, xw, ys, dA);
+    int kA = row_finish<ST, BC, F>(a, S, xw, xin, ys, dA, mA, qxA, qyA), kB;
     int sc = 0;  // LDS slot of the current row
     if (LW > 1) {
         if (lane == 0) qedge[0][w][0] = qxA;
         if (lane == kWave - 1) qedge[0][w][1] = qxA;
     }
 
-    // One row: issue the look-ahead row's loads, finish it, publish its edge
-    // Q_x, then collide and store the current row.
-    auto row = [&](int y, float(&dC)[18], const Mom &mC, int kC, float qxC, float(&dN)[18], Mom &mN, int &kN,
+    // One row (k rows into the march): issue the look-ahead row's loads,
+    // finish it, publish its edge Q_x, then collide and store the current row.
+    auto row = [&](int k, float(&dC)[18], const Mom &mC, int kC, float qxC, float(&dN)[18], Mom &mN, int &kN,
                    float &qxN, float &qyN) {
-        row_issue<ST, BC>(a, S, xw, y + 1, dN);
-        const int k = y - y0, r = k & (kHaloRows - 1);
+        const int y = ys + dir * k;
+        row_issue<ST, BC>(a, S, xw, y + dir, dN);
+        const int r = k & (kHaloRows - 1);
         if ((edge_l || edge_r) && r == 0 && k != 0)
-            qh = halo_chunk<ST, BC, F>(a, S, x0, lane, y, y1 - 1, edge_l, edge_r);
+            qh = halo_chunk<ST, BC, F>(a, S, x0, lane, y, dir, y0, y1 - 1, edge_l, edge_r);
         float qhl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qh), r));
         float qhr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qh), kHaloRows + r));
-        kN = row_finish<ST, BC, F>(a, S, xw, xin, y + 1, dN, mN, qxN, qyN);
+        kN = row_finish<ST, BC, F>(a, S, xw, xin, y + dir, dN, mN, qxN, qyN);
         if (LW > 1) {
             const int sn = sc == 2 ? 0 : sc + 1;
             if (lane == 0) qedge[sn][w][0] = qxN;
@@ -754,19 +762,22 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
             if (!edge_r) qhr = qedge[sc][wr][0];
             sc = sn;
         }
-        collide_store<ST, BC, F>(a, D, dC, mC, kC, lane, qxC, qhl, qhr, qyp, qyN, owned, vo, step);
-        vo += pitch_b;
+        // Q_y at y - 1 and y + 1
+        const float qym = dir > 0 ? qyb : qyN, qyq = dir > 0 ? qyN : qyb;
+        collide_store<ST, BC, F>(a, D, dC, mC, kC, lane, qxC, qhl, qhr, qym, qyq, owned, vo, step);
+        vo += dvo;
     };
-    int y = y0;
+    const int rows = y1 - y0;
+    int k = 0;
     for (;;) {
-        if (y >= y1) break;
-        row(y, dA, mA, kA, qxA, dB, mB, kB, qxB, qyB);
-        qyp = qyA;
-        ++y;
-        if (y >= y1) break;
-        row(y, dB, mB, kB, qxB, dA, mA, kA, qxA, qyA);
-        qyp = qyB;
-        ++y;
+        if (k >= rows) break;
+        row(k, dA, mA, kA, qxA, dB, mB, kB, qxB, qyB);
+        qyb = qyA;
+        ++k;
+        if (k >= rows) break;
+        row(k, dB, mB, kB, qxB, dA, mA, kA, qxA, qyA);
+        qyb = qyB;
+        ++k;
     }
 }
 
