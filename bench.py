@@ -50,13 +50,31 @@ def measured_traffic(key: str, nodes: int):
     return e.get("bytes_per_launch")
 
 
-def time_gpu(n: int, storage: str, steps: int, warmup: int, strip_rows: int = 0):
+def bounded_case(kind: str, storage: str):
+    """The bounded configurations: the large-dT cavity at 512^2 (walls on all
+    sides, Sutherland viscosity) and the acoustic channel 2048 x 256 (inlet,
+    outlet, periodic in y)."""
+    from paper_1109_6672_amd import workloads as W
+
+    if kind == "cavity512":
+        p = W.cavity(512, 1e5, 1.2, 0.06, sutherland=True, storage=storage)
+        p.update(s_e=1.5, s_zeta=1.5)
+        return p, W.conduction_fields(p)
+    p = W.channel(2048, 256, U0=0.01, period=200.0, storage=storage)
+    return p, W.rest_fields(p)
+
+
+def time_gpu(n: int, storage: str, steps: int, warmup: int, strip_rows: int = 0, case=None):
     import torch
 
     from paper_1109_6672_amd import lbddf, workloads as W
 
-    p = W.periodic(n, storage=storage)
-    fields = W.gaussian_fields(p, sigma=1e-3)
+    if case is None:
+        p = W.periodic(n, storage=storage)
+        fields = W.gaussian_fields(p, sigma=1e-3)
+    else:
+        p, fields = bounded_case(case, storage)
+    n_nodes = p["nx"] * p["ny"]
     s = lbddf.Solver(p, device=0)
     s.init(*fields)
     del fields
@@ -74,7 +92,7 @@ def time_gpu(n: int, storage: str, steps: int, warmup: int, strip_rows: int = 0)
     wall = time.perf_counter() - t0
     ms = start.elapsed_time(stop)
     d = s.diag(check=False)
-    nodes = n * n
+    nodes = n_nodes
     out = dict(n=n, storage=storage, steps=steps, ms_total=ms, ms_per_step=ms / steps, wall_s=wall,
                mlups=nodes * steps / (ms * 1e-3) / 1e6, strip_rows=s.strip_rows, bad_nodes=d["bad"])
     out["gbs"] = BYTES_PER_NODE[storage] * nodes / (out["ms_per_step"] * 1e-3) / 1e9
@@ -179,6 +197,10 @@ def main():
             r = time_gpu(n, storage, args.steps, args.warmup)
             extra[f"{storage}_{n}"] = {k: r[k] for k in ("mlups", "gbs", "ms_per_step", "strip_rows")}
             print(f"# {storage} {n}^2: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        for case, storage in (("cavity512", "f32"), ("cavity512", "f16"), ("channel2048x256", "f32")):
+            r = time_gpu(0, storage, args.steps, args.warmup, case=case)
+            extra[f"{storage}_{case}"] = {k: r[k] for k in ("mlups", "gbs", "ms_per_step", "strip_rows")}
+            print(f"# {storage} {case}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     nodes = args.n * args.n
     alg = BYTES_PER_NODE["f32"] * nodes
     achieved = alg / (head["ms_per_step"] * 1e-3) / 1e9

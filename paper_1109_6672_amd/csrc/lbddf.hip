@@ -1103,10 +1103,13 @@ void set_strip(lb_handle *h) {
     a.tiles_x = (a.nx + kTile - 1) / kTile;
     int R = h->strip_user;
     if (R <= 0) {
-        // 8-row strips (measured best on 8192^2); shorter ones when the grid
-        // would not give 256 CUs enough wavefronts
+        // 8-row strips (measured best on 8192^2); shorter ones, down to 1 row,
+        // while the grid would give fewer blocks than the 256 CUs (measured
+        // on 512^2 and 2048 x 256)
+        const int lw = h->p.storage == LB_STORE_F32 ? kLock<LB_STORE_F32> : kLock<LB_STORE_F16>;
+        const long long bcols = (a.tiles_x + lw - 1) / lw;
         R = 8;
-        while (R > 4 && (long long)a.tiles_x * ((a.ny + R - 1) / R) < 16384) R >>= 1;
+        while (R > 1 && bcols * ((a.ny + R - 1) / R) < 256) R >>= 1;
     }
     a.strip_rows = R;
     a.n_strips = (a.ny + R - 1) / R;
@@ -1510,6 +1513,7 @@ namespace {
 constexpr int kMaxSlots = 512;
 constexpr int kMaxItems = 1 << 18;
 constexpr int kMultiBlocks = 2048;  // fixed grid of the packed step: 8192 wavefronts
+constexpr int kServeStripRows = 4;   // strip height of every served grid (measured: 4 beats 8)
 
 double now_s() {
     using namespace std::chrono;
@@ -1655,6 +1659,10 @@ lb_status admit(lbs_server *S) {
             pool_free(S, off, r.bytes);
             return st;
         }
+        // the packed step gets its parallelism from many grids: long strips
+        // (fewer halo rows per row computed) whatever the grid's size
+        h->strip_user = kServeStripRows;
+        set_strip(h);
         const size_t N = (size_t)r.p.nx * r.p.ny;
         if (r.init.empty())
             st = lb_init(h, nullptr, nullptr, nullptr, nullptr);
