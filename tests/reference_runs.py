@@ -5,9 +5,12 @@ s_e = s_zeta = 1.5, pure-conduction start, 200,000 steps.
 
 Runs only the FP64 oracle and writes its macroscopic fields (rho, ux, uy, T)
 with the step count to an .npz file; checkpoints every `--every` steps so
-that an interrupted run resumes.  Usage:
+that an interrupted run resumes.  `--golden` also writes the fields on every
+`--stride`-th node in x and y (the fixture tests/golden/large_dt_512_sample.npz
+that tests/test_gpu_validation.py compares the GPU run with).  Usage:
 
-    python -m tests.reference_runs --out ref.npz [--steps 200000] [--every 10000]
+    python -m tests.reference_runs --out ref.npz [--steps 200000] [--every 10000] \
+        [--golden tests/golden/large_dt_512_sample.npz --stride 8]
 """
 from __future__ import annotations
 
@@ -41,7 +44,12 @@ def main():
     ap.add_argument("--out", required=True)
     ap.add_argument("--steps", type=int, default=200_000)
     ap.add_argument("--every", type=int, default=10_000)
+    ap.add_argument("--golden", default="")
+    ap.add_argument("--stride", type=int, default=8)
     args = ap.parse_args()
+    if args.golden and os.path.exists(args.out):
+        write_golden(args.out, args.golden, args.stride)
+        return
     p, f = large_dt_512()
     o = O.Oracle(p).init(*f)
     ck = args.out + ".ckpt.npz"
@@ -62,6 +70,17 @@ def main():
     rho, ux, uy, T = o.macros()
     np.savez(args.out, rho=rho, ux=ux, uy=uy, T=T, time=n)
     print(f"wrote {args.out}", flush=True)
+    if args.golden:
+        write_golden(args.out, args.golden, args.stride)
+
+
+def write_golden(full: str, golden: str, stride: int):
+    z = np.load(full)
+    off = stride // 2
+    sl = (slice(off, None, stride), slice(off, None, stride))
+    np.savez_compressed(golden, rho=z["rho"][sl], ux=z["ux"][sl], uy=z["uy"][sl], T=z["T"][sl],
+                        time=z["time"], stride=stride, offset=off)
+    print(f"wrote {golden} ({z['rho'][sl].shape} nodes every {stride} from {off})", flush=True)
 
 
 if __name__ == "__main__":
