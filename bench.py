@@ -133,6 +133,10 @@ def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 2
     pool = lbddf.load().lbs_pool_overhead() + sum(lbddf.state_bytes(r["params"]) + 256 for r in reqs)
     packed, srv, _ = SV.run_server(reqs, pool, k_steps=k_steps, tol=tol, max_steps=cap)
     srv.close()
+    reqs16 = W.serving_mix(n_requests, sizes=sizes, rate=50.0, storage="f16")
+    pool16 = lbddf.load().lbs_pool_overhead() + sum(lbddf.state_bytes(r["params"]) + 256 for r in reqs16)
+    packed16, srv, _ = SV.run_server(reqs16, pool16, storage="f16", k_steps=k_steps, tol=tol, max_steps=cap)
+    srv.close()
     seq = SV.run_sequential(reqs, k_steps=k_steps, tol=tol, max_steps=cap)
     keep = ("p50_s", "p99_s", "solves_per_s", "mlups", "wall_s", "states")
     return {
@@ -141,6 +145,7 @@ def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 2
                     f"residual checked every {k_steps} steps, tol {tol:g}, plateau test, cap {cap} steps",
         "packed": {k: packed[k] for k in keep},
         "one_at_a_time": {k: seq[k] for k in keep},
+        "packed_f16_storage": {k: packed16[k] for k in keep},
         "solves_per_s_ratio": packed["solves_per_s"] / seq["solves_per_s"],
         "p99_ratio": seq["p99_s"] / packed["p99_s"],
     }

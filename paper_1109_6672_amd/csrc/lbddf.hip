@@ -13,12 +13,17 @@
 //    the collision and the codec all work on these deviations, which keeps
 //    FP32 (and the 16-bit codecs) accurate for the small perturbations of
 //    low-Mach flows.
-//  * One wavefront owns a strip of 64 aligned columns x R rows and marches up
-//    the strip.  The x-neighbours of the correction term's Q (Eq. 48-50) come
-//    from the adjacent lanes, the y-neighbours from the previous and the
-//    look-ahead row kept in registers; the two columns just outside the tile
-//    are gathered for 32 rows at a time, one row per lane, and read out with
-//    readlane.  No LDS and no barrier is needed and each row is gathered once.
+//  * A wavefront owns 64 aligned columns of a strip of R rows and marches
+//    through it, one row per iteration; the wavefronts of a block own
+//    adjacent tiles of one strip and march in lockstep (one barrier per row),
+//    up on even strips and down on odd ones.  The x-neighbours of the
+//    correction term's Q (Eq. 48-50) come from the adjacent lanes and, at the
+//    tile edges, through LDS from the neighbouring wavefronts; the
+//    y-neighbours come from the previous and the look-ahead row kept in
+//    registers.  Only the two outer wavefronts of a block gather the columns
+//    just outside it, for 32 rows at a time (one row per lane).  Each row is
+//    gathered once, and neighbouring tiles and strips read the lines they
+//    share at the same time, while those are in L2.
 //  * Boundary nodes gather the populations of the interior node they
 //    extrapolate from instead of their own (non-equilibrium extrapolation),
 //    so the wavefront's loads stay uniform; the rebuild is a short divergent

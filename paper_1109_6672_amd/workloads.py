@@ -247,7 +247,7 @@ def conduction_fields(p: dict, amp: float = 1e-6, k: int = 3):
 
 def serving_mix(n_requests: int, sizes=(64, 128, 256, 512, 1024), Ra_range=(1e3, 1e6), dT_range=(0.02, 1.2),
                 rate: float = 50.0, Pr: float = 0.71, storage: str = "f32", k: int = 5, u_target: float = 0.05,
-                tau_min: float = 0.56):
+                tau_min: float = 0.56, nu_max: float = 0.1):
     """Seeded stream of cavity requests with Poisson arrivals.
 
     Per request, from one SplitMix64 stream (seed SEED_BASE + k): the
@@ -255,8 +255,9 @@ def serving_mix(n_requests: int, sizes=(64, 128, 256, 512, 1024), Ra_range=(1e3,
     `sizes`), Ra (log-uniform) and dT/T0 (uniform).  The viscosity is chosen
     so that the buoyancy velocity nu sqrt(Ra / Pr) / H equals `u_target`,
     with tau_f(T_r) = 3 nu + 1/2 kept >= tau_min (requests at that bound are
-    flagged "under_resolved"); large dT (> 0.2) uses the Sutherland law and
-    energy-mode rates s_e = s_zeta = 1.5.  Returns a
+    flagged "under_resolved") and nu <= nu_max (flagged "viscosity_capped");
+    large dT (> 0.2) uses the Sutherland law and energy-mode rates
+    s_e = s_zeta = 1.5.  Returns a
     list of dicts with keys t (arrival, s), params, n, Ra, dT, flags.
     """
     u = uniform01(SEED_BASE + k, 4 * n_requests).reshape(n_requests, 4)
@@ -272,6 +273,11 @@ def serving_mix(n_requests: int, sizes=(64, 128, 256, 512, 1024), Ra_range=(1e3,
         if 3 * nu + 0.5 < tau_min:
             nu = (tau_min - 0.5) / 3
             flags.append("under_resolved")
+        elif nu > nu_max:
+            # the paper's viscosities stay at or below 0.1 (Sec. IV-C); larger
+            # ones (tau_f near 2 at a hot wall) diverge at large dT
+            nu = nu_max
+            flags.append("viscosity_capped")
         p = cavity(n, Ra, dT, nu, Pr=Pr, sutherland=dT > 0.2, storage=storage)
         if dT > 0.2:
             # large dT: energy-mode rates untied from tau_f (allowed for
