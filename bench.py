@@ -161,6 +161,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit and smaller-grid runs")
     ap.add_argument("--no-serving", action="store_true", help="skip the packed-server comparison")
+    ap.add_argument("--serving-requests", type=int, default=24, help="requests in the serving mix")
+    ap.add_argument("--serving-sizes", default="64,128,256", help="grid edges of the serving mix")
     ap.add_argument("--only", default="", help="storage of a single run (profiling): f32 | f16 | bf16")
     ap.add_argument("--copy-only", action="store_true",
                     help="HBM counter calibration: 5 plain device copies of 2 GiB (torch copy kernel)")
@@ -233,7 +235,8 @@ def main():
         "bad_nodes": head["bad_nodes"],
     }
     if not args.no_serving:
-        line["serving"] = serving_compare()
+        line["serving"] = serving_compare(args.serving_requests,
+                                          tuple(int(v) for v in args.serving_sizes.split(",")))
         print(f"# serving: {line['serving']['packed']['solves_per_s']:.1f} solves/s packed, "
               f"{line['serving']['one_at_a_time']['solves_per_s']:.1f} one at a time", file=sys.stderr, flush=True)
     if not args.no_cpu:
