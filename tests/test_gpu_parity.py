@@ -131,6 +131,28 @@ def test_populations_match_the_oracle(gpu):
     assert np.max(np.abs(gp - rp) / scale) < 1e-5
 
 
+@pytest.mark.parametrize("storage,mant", [("f16", 10), ("bf16", 7)])
+def test_16bit_codec_rounding_bound(gpu, storage, mant):
+    """Stored values are the deviations from the rest equilibria, rounded
+    stochastically to the 16-bit format (after a power-of-two plane scale for
+    FP16): each decoded population lies within one unit in the last place of
+    its deviation, 2^-mant |dev| (or the format's smallest step), of the FP64
+    equilibrium of the initial fields."""
+    from oracle import oracle as O
+
+    p = W.periodic(130, 70, storage=storage)
+    f = W.gaussian_fields(p, sigma=1e-2)
+    gp = lbddf.Solver(p).init(*f).populations()
+    rp = O.Oracle(p).init(*f).pops()
+    rest = O.Oracle(p).init(*W.rest_fields(p)).pops()[:, :1, :1]
+    dev = np.abs(rp - rest)
+    tiny = 2.0 ** -24 if storage == "f16" else 2.0 ** -133
+    bound = np.maximum(dev * 2.0 ** -mant, tiny) + 1e-7 * np.abs(rp)
+    err = np.abs(gp - rp)
+    print(f"[case] {storage} codec: max err / bound {np.max(err / bound):.3f}", flush=True)
+    assert np.all(err <= bound)
+
+
 def test_conservation_and_diagnostics(gpu):
     p = W.periodic(256, 192)
     f = W.gaussian_fields(p, sigma=1e-3)
