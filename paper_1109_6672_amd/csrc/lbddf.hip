@@ -1109,12 +1109,12 @@ void set_strip(lb_handle *h) {
     int R = h->strip_user;
     if (R <= 0) {
         // 8-row strips (measured best on 8192^2); shorter ones, down to 1 row,
-        // while the grid would give fewer blocks than the 256 CUs (measured
-        // on 512^2 and 2048 x 256)
+        // while the grid would give fewer than 2048 wavefronts, 8 per CU
+        // (measured on 512^2 and 2048 x 256 in FP32 and FP16)
         const int lw = h->p.storage == LB_STORE_F32 ? kLock<LB_STORE_F32> : kLock<LB_STORE_F16>;
         const long long bcols = (a.tiles_x + lw - 1) / lw;
         R = 8;
-        while (R > 1 && bcols * ((a.ny + R - 1) / R) < 256) R >>= 1;
+        while (R > 1 && bcols * lw * ((a.ny + R - 1) / R) < 2048) R >>= 1;
     }
     a.strip_rows = R;
     a.n_strips = (a.ny + R - 1) / R;
