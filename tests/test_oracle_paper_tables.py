@@ -1,11 +1,12 @@
-"""The oracle against the numbers the paper prints (Table I)."""
+"""The oracle against the numbers the paper prints (Tables I and II)."""
 import json
 import os
 
 import pytest
 
 from oracle import oracle as O
-from paper_1109_6672_amd import workloads as W
+from paper_1109_6672_amd import postproc as P, workloads as W
+from paper_1109_6672_amd.serving import Plateau
 
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -36,3 +37,28 @@ def test_table1_couette_lower_wall_temperature(row):
     Er = abs((T[0, 0] - 1) - (Ta_exact - 1)) / (Ta_exact - 1)
     assert Er < 0.01
     assert abs(T[0, 0] - T_paper) < 0.01 * (T_paper - 1)
+
+
+def test_table2_cavity_ra1e3():
+    """Small-dT natural convection at Ra = 1e3 (Sec. IV-C) run to convergence on
+    64 x 64 nodes (the paper: 100 x 100), mu_r = 0.05: Nu, u_max and v_max
+    within 2 % of the 'Present' row of Table II, the positions within two
+    lattice spacings."""
+    with open(os.path.join(GOLD, "table2_cavity.json")) as fh:
+        tab = json.load(fh)
+    row = dict(zip(tab["columns"], next(r for r in tab["rows"] if r[0] == 1e3)))
+    p = W.cavity(64, 1e3, 0.02, 0.05)
+    o = O.Oracle(p).init(*W.noisy_temperature_fields(p))
+    o.residual(update=True)
+    pl, r = Plateau(), 1.0
+    while o.time < 150_000:
+        o.step(500)
+        r = o.residual(update=True)
+        if r < 1e-9 or pl.update(r):
+            break
+    assert r < 1e-8
+    m = P.cavity_metrics(p, *o.macros()[1:])
+    for k in ("Nu", "u_max", "v_max"):
+        assert abs(m[k] / row[k] - 1) < 0.02, (k, m[k], row[k])
+    for k in ("y_max", "x_max"):
+        assert abs(m[k] - row[k]) < 2 / 63 + 1e-9, (k, m[k], row[k])
