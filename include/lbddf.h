@@ -88,7 +88,11 @@ typedef struct {
     int32_t coupled;     /* 1: theta-coupled Eq. 18; 0: decoupled theta = 1, p = rho R T0 (Eq. 8) */
     int32_t collision;   /* lb_collision */
     int32_t visc;        /* lb_visc */
-    int32_t rho_extrap;  /* lb_rho_extrap: density of a wall node with prescribed T */
+    int32_t rho_extrap;  /* lb_rho_extrap: density of a wall node: LB_RHO_PRESSURE
+                            extrapolates p = rho R T from the interior node with the
+                            hydrostatic balance of the force, p_b = p_f
+                            exp(g (y_f - y_b) / (R (T_f + T_b) / 2));
+                            LB_RHO_DENSITY takes rho_f */
     double rho0, T0, R;  /* reference state; R * T0 = 1/3 */
     double b;            /* degrees of freedom, gamma = (b + 2) / b */
     double Pr;           /* Pr = (tau_f - 1/2) / tau_h; tau_hf = tau_f / (Pr - 1) */

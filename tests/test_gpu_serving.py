@@ -56,13 +56,16 @@ def test_server_matches_single_grid(gpu):
         assert max(e_srv) < TOL["f32"] and max(e_one) < TOL["f32"]
 
 
-def test_alone_and_in_the_mix_are_identical(gpu):
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_alone_and_in_the_mix_are_identical(gpu, storage):
+    """Bit for bit, also with FP16 storage, whose stochastic rounding draws on
+    the node's index within its grid and the time step only."""
     reqs = _requests()
     target = 1
-    alone = lbddf.Server(_pool(reqs), k_steps=50)
+    alone = lbddf.Server(_pool(reqs), storage=storage, k_steps=50)
     a = alone.submit(reqs[target][0], _fields(*reqs[target]), tol=0.0, max_steps=400)
     _run_to_end(alone)
-    mixed = lbddf.Server(_pool(reqs), k_steps=50)
+    mixed = lbddf.Server(_pool(reqs), storage=storage, k_steps=50)
     ids = [mixed.submit(p, _fields(p, k), tol=0.0, max_steps=400 if i == target else 200 + 100 * i)
            for i, (p, k) in enumerate(reqs)]
     _run_to_end(mixed)
