@@ -64,12 +64,18 @@ def splitmix64(seed: int, count: int, start: int = 0) -> np.ndarray:
     seed + (k+1) * 0x9E3779B97F4A7C15 (mod 2**64), so the stream can be
     evaluated for any index range without generating its prefix.
     """
-    k = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+    z = np.arange(start + 1, start + count + 1, dtype=np.uint64)
+    t = np.empty_like(z)
     with np.errstate(over="ignore"):
-        z = np.uint64(seed & 0xFFFFFFFFFFFFFFFF) + k * _GAMMA
-        z = (z ^ (z >> np.uint64(30))) * _M1
-        z = (z ^ (z >> np.uint64(27))) * _M2
-        z = z ^ (z >> np.uint64(31))
+        # in place: the same arithmetic without a temporary per operation
+        np.multiply(z, _GAMMA, out=z)
+        np.add(z, np.uint64(seed & 0xFFFFFFFFFFFFFFFF), out=z)
+        for sh, m in ((30, _M1), (27, _M2)):
+            np.right_shift(z, np.uint64(sh), out=t)
+            np.bitwise_xor(z, t, out=z)
+            np.multiply(z, m, out=z)
+        np.right_shift(z, np.uint64(31), out=t)
+        np.bitwise_xor(z, t, out=z)
     return z
 
 

@@ -1,6 +1,8 @@
 """Validation of the HIP path at the full sizes of the paper's test problems,
 against what the paper and the mathematics fix there:
 
+* the bench workload (periodic 8192 x 8192) element by element against the
+  FP64 oracle after 5 steps;
 * the small-dT cavity (128 x 128, Ra = 1e4) run to convergence against the
   'Present' row of Table II;
 * the acoustic channel (2048 x 256, sinusoidal source at x = 0) against the
@@ -40,6 +42,35 @@ def _converge(s, check=1000, tol=1e-8, cap=600_000):
         if pl.update(r):
             return "plateau", r
     return "step_cap", r
+
+
+@pytest.fixture(scope="module")
+def bench_reference():
+    """The FP64 oracle on the workload bench.py times (periodic 8192 x 8192,
+    Gaussian sigma = 1e-3), 5 steps: about 20 GB of host memory, a few
+    seconds per step on the host cores."""
+    from oracle import oracle as O
+
+    p = W.periodic(8192)
+    f = W.gaussian_fields(p, sigma=1e-3)
+    print("[case] oracle on the bench workload, periodic 8192x8192, 5 steps", flush=True)
+    o = O.Oracle(p).init(*f).step(5)
+    ref = o.macros()
+    del o
+    return p, f, ref
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_bench_workload_at_full_size_against_the_oracle(bench_reference, storage):
+    """Full-size parity in the launch configuration bench.py times (8192^2,
+    lockstep blocks, 8-row strips), element by element after 5 steps."""
+    p, f, ref = bench_reference
+    s = lbddf.Solver(dict(p, storage=storage)).init(*f).step(5)
+    e = rel_errors(s.macros(), ref)
+    print(f"[case] bench workload 8192x8192 {storage}, 5 steps (strip rows {s.strip_rows}): rel err rho {e[0]:.3e} "
+          f"u {e[1]:.3e} T {e[2]:.3e}", flush=True)
+    s.close()
+    assert max(e) < TOL[storage], e
 
 
 def test_small_dT_cavity_reproduces_table_ii():
