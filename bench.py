@@ -163,6 +163,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the packed-server comparison")
     ap.add_argument("--serving-requests", type=int, default=24, help="requests in the serving mix")
     ap.add_argument("--serving-sizes", default="64,128,256", help="grid edges of the serving mix")
+    ap.add_argument("--serving-only", action="store_true", help="only the serving comparison (profiling)")
     ap.add_argument("--only", default="", help="storage of a single run (profiling): f32 | f16 | bf16")
     ap.add_argument("--copy-only", action="store_true",
                     help="HBM counter calibration: 5 plain device copies of 2 GiB (torch copy kernel)")
@@ -186,6 +187,11 @@ def main():
         dt = (time.perf_counter() - t0) / 5
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": x.numel() * 4,
                           "copy_GBs": 2 * x.numel() * 4 / dt / 1e9}), flush=True)
+        return
+
+    if args.serving_only:
+        print(json.dumps(serving_compare(args.serving_requests,
+                                         tuple(int(v) for v in args.serving_sizes.split(",")))), flush=True)
         return
 
     if args.only:
