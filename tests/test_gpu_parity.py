@@ -153,7 +153,48 @@ def test_16bit_codec_rounding_bound(gpu, storage, mant):
     assert np.all(err <= bound)
 
 
-def test_conservation_and_diagnostics(gpu):
+@pytest.mark.parametrize("storage", ["f16", "bf16"])
+def test_16bit_stochastic_rounding_is_unbiased(gpu, storage):
+    """A uniform state stores the same deviation x at every node. Stochastic
+    rounding puts each stored value on one of the two format neighbours of x
+    (FP16 after its power-of-two plane scale, BF16 directly), taking the upper
+    one with probability (x - lo) / (hi - lo): over 65,536 nodes the mean of
+    the stored values sits on x within a few standard errors, where rounding to
+    nearest would sit up to half a step away. The neighbours and the exact x
+    come from the format's definition and the FP64 oracle, not from the
+    kernel."""
+    from oracle import oracle as O
+
+    p = W.periodic(256, 256, storage=storage)
+    shape = (p["ny"], p["nx"])
+    # the values the library receives (it takes the fields in FP32)
+    vals = [float(np.float32(v)) for v in (1.02, 0.05, -0.03, 1.05)]
+    f = tuple(np.full(shape, v) for v in vals)
+    gp = lbddf.Solver(p).init(*f).populations()
+    rp = O.Oracle(p).init(*f).pops()
+    rest = O.Oracle(p).init(*W.rest_fields(p)).pops()[:, 0, 0]
+    mant = 10 if storage == "f16" else 7
+    n = gp[0].size
+    straddled = 0
+    for q in range(18):
+        a = q % 9
+        s = 1.0 if storage == "bf16" else (512.0 if a == 0 else (2048.0 if a < 5 else 8192.0))
+        x = (rp[q, 0, 0] - rest[q]) * s
+        obs = (gp[q].ravel() - rest[q]) * s
+        gap = 2.0 ** (np.floor(np.log2(abs(x))) - mant)
+        lo = np.floor(x / gap) * gap
+        p_up = (x - lo) / gap
+        assert np.all(np.abs(obs - x) < gap * (1 + 1e-3)), (q, x, np.unique(obs))
+        assert len(np.unique(np.round(obs / gap * 8) / 8)) <= 2, (q, np.unique(obs))
+        bias = (obs.mean() - x) / gap
+        print(f"[case] {storage} plane {q}: p_up {p_up:.3f} observed {np.mean(obs > x):.3f} bias {bias:+.4f} step",
+              flush=True)
+        assert abs(bias) < 5 * 0.5 / np.sqrt(n) + 0.02
+        if 0.1 < p_up < 0.9:
+            straddled += 1
+            assert abs(np.mean(obs > x) - p_up) < 5 * np.sqrt(p_up * (1 - p_up) / n) + 0.02
+    assert straddled >= 6
+
     p = W.periodic(256, 192)
     f = W.gaussian_fields(p, sigma=1e-3)
     s = lbddf.Solver(p).init(*f)
