@@ -112,8 +112,12 @@ typedef struct lb_handle lb_handle;
 lb_status lb_validate(const lb_params *p);
 
 /* Bytes of device memory one grid needs: two population buffers of 18 planes
- * (row pitch nx rounded up to 64 nodes), a temperature snapshot plane and
- * reduction scratch.  0 when the parameters are invalid. */
+ * (row pitch nx rounded up to 64 nodes; inside each buffer the f^ half and
+ * the h- half each keep the rows of their 9 populations next to each other,
+ * [y][a][x]; lb_populations returns [18][ny][nx] whatever this internal
+ * layout, and the lb_save image is opaque), a temperature snapshot plane and
+ * reduction scratch.  0 when the parameters
+ * are invalid. */
 size_t lb_state_bytes(const lb_params *p);
 
 /* Binds a grid to the caller's device buffer and HIP stream (a hipStream_t,
@@ -162,8 +166,8 @@ lb_status lb_load(lb_handle *h, const void *host_buf);
 
 /* Launch tuning of the step kernel: rows per strip (power of two 1..256;
  * each block of wavefronts marches through one strip of rows), 0 restores
- * the automatic choice (8 rows, halved down to 1 while the grid would give
- * fewer than 2048 wavefronts).  Results do not depend on it.  Returns LB_EINVAL
+ * the automatic choice (8 rows with FP32 storage, 16 with FP16/BF16,
+ * halved down to 1 while the grid would give fewer than 2048 wavefronts).  Results do not depend on it.  Returns LB_EINVAL
  * for other values. */
 lb_status lb_set_strip_rows(lb_handle *h, int rows);
 int lb_strip_rows(const lb_handle *h);
