@@ -124,31 +124,40 @@ def cpu_baseline(seconds: float):
 
 
 def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 200, tol: float = 1e-8,
-                    cap: int = 100_000):
+                    cap: int = 100_000, modes=("packed", "f16", "seq"), progress: float = 0.0):
     """The continuous-batching server against one solve per launch, on the
-    same seeded stream of cavity requests (Poisson arrivals, 50 per second)."""
+    same seeded stream of cavity requests (Poisson arrivals, 50 per second).
+    modes picks the runs: packed (FP32), f16 (packed, FP16 storage), seq (one
+    solve per launch, FP32)."""
     from paper_1109_6672_amd import lbddf, serving as SV, workloads as W
 
-    reqs = W.serving_mix(n_requests, sizes=sizes, rate=50.0)
-    pool = lbddf.load().lbs_pool_overhead() + sum(lbddf.state_bytes(r["params"]) + 256 for r in reqs)
-    packed, srv, _ = SV.run_server(reqs, pool, k_steps=k_steps, tol=tol, max_steps=cap)
-    srv.close()
-    reqs16 = W.serving_mix(n_requests, sizes=sizes, rate=50.0, storage="f16")
-    pool16 = lbddf.load().lbs_pool_overhead() + sum(lbddf.state_bytes(r["params"]) + 256 for r in reqs16)
-    packed16, srv, _ = SV.run_server(reqs16, pool16, storage="f16", k_steps=k_steps, tol=tol, max_steps=cap)
-    srv.close()
-    seq = SV.run_sequential(reqs, k_steps=k_steps, tol=tol, max_steps=cap)
     keep = ("p50_s", "p99_s", "solves_per_s", "mlups", "wall_s", "states")
-    return {
+    out = {
         "workload": f"{n_requests} differentially heated cavity requests, edges {'/'.join(map(str, sizes))}, "
                     "Poisson arrivals 50/s, Ra log-uniform 1e3..1e6, dT/T0 uniform 0.02..1.2, FP32, "
                     f"residual checked every {k_steps} steps, tol {tol:g}, plateau test, cap {cap} steps",
-        "packed": {k: packed[k] for k in keep},
-        "one_at_a_time": {k: seq[k] for k in keep},
-        "packed_f16_storage": {k: packed16[k] for k in keep},
-        "solves_per_s_ratio": packed["solves_per_s"] / seq["solves_per_s"],
-        "p99_ratio": seq["p99_s"] / packed["p99_s"],
     }
+    reqs = W.serving_mix(n_requests, sizes=sizes, rate=50.0)
+    if "packed" in modes:
+        pool = lbddf.load().lbs_pool_overhead() + sum(lbddf.state_bytes(r["params"]) + 256 for r in reqs)
+        packed, srv, _ = SV.run_server(reqs, pool, k_steps=k_steps, tol=tol, max_steps=cap, progress=progress)
+        srv.close()
+        out["packed"] = {k: packed[k] for k in keep}
+    if "f16" in modes:
+        reqs16 = W.serving_mix(n_requests, sizes=sizes, rate=50.0, storage="f16")
+        pool16 = lbddf.load().lbs_pool_overhead() + sum(lbddf.state_bytes(r["params"]) + 256 for r in reqs16)
+        packed16, srv, _ = SV.run_server(reqs16, pool16, storage="f16", k_steps=k_steps, tol=tol, max_steps=cap,
+                                         progress=progress)
+        srv.close()
+        del reqs16
+        out["packed_f16_storage"] = {k: packed16[k] for k in keep}
+    if "seq" in modes:
+        seq = SV.run_sequential(reqs, k_steps=k_steps, tol=tol, max_steps=cap, progress=progress)
+        out["one_at_a_time"] = {k: seq[k] for k in keep}
+    if "packed" in out and "one_at_a_time" in out:
+        out["solves_per_s_ratio"] = out["packed"]["solves_per_s"] / out["one_at_a_time"]["solves_per_s"]
+        out["p99_ratio"] = out["one_at_a_time"]["p99_s"] / out["packed"]["p99_s"]
+    return out
 
 
 def main():
@@ -163,7 +172,11 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the packed-server comparison")
     ap.add_argument("--serving-requests", type=int, default=24, help="requests in the serving mix")
     ap.add_argument("--serving-sizes", default="64,128,256", help="grid edges of the serving mix")
-    ap.add_argument("--serving-only", action="store_true", help="only the serving comparison (profiling)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the serving comparison, with progress lines on stderr")
+    ap.add_argument("--serving-modes", default="packed,f16,seq",
+                    help="runs of the serving comparison: packed, f16, seq (one solve per launch)")
+    ap.add_argument("--serving-cap", type=int, default=100_000, help="step cap per request")
     ap.add_argument("--only", default="", help="storage of a single run (profiling): f32 | f16 | bf16")
     ap.add_argument("--copy-only", action="store_true",
                     help="HBM counter calibration: 5 plain device copies of 2 GiB (torch copy kernel)")
@@ -191,7 +204,9 @@ def main():
 
     if args.serving_only:
         print(json.dumps(serving_compare(args.serving_requests,
-                                         tuple(int(v) for v in args.serving_sizes.split(",")))), flush=True)
+                                         tuple(int(v) for v in args.serving_sizes.split(",")),
+                                         cap=args.serving_cap, modes=tuple(args.serving_modes.split(",")),
+                                         progress=20.0)), flush=True)
         return
 
     if args.only:
@@ -242,7 +257,8 @@ def main():
     }
     if not args.no_serving:
         line["serving"] = serving_compare(args.serving_requests,
-                                          tuple(int(v) for v in args.serving_sizes.split(",")))
+                                          tuple(int(v) for v in args.serving_sizes.split(",")),
+                                          cap=args.serving_cap)
         print(f"# serving: {line['serving']['packed']['solves_per_s']:.1f} solves/s packed, "
               f"{line['serving']['one_at_a_time']['solves_per_s']:.1f} one at a time", file=sys.stderr, flush=True)
     if not args.no_cpu:

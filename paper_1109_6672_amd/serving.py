@@ -4,6 +4,7 @@ first out).  Both report per-request time-to-finish from the arrival time,
 p50/p99 latency, solves per second and aggregate MLUPS."""
 from __future__ import annotations
 
+import sys
 import time
 
 import numpy as np
@@ -40,14 +41,29 @@ class Plateau:
         return False
 
 
-def run_server(requests, pool_bytes, storage="f32", k_steps=200, tol=1e-6, max_steps=20000, realtime=True):
-    """Drives a Server with the requests' arrival times (seconds from start)."""
+def _report(every, last, now, label, done, total, extra=""):
+    """A progress line on stderr at most every `every` seconds (0: never)."""
+    if every and now - last >= every:
+        print(f"[serving] {label}: {done}/{total} finished after {now:.0f} s{extra}", file=sys.stderr, flush=True)
+        return now
+    return last
+
+
+def run_server(requests, pool_bytes, storage="f32", k_steps=200, tol=1e-6, max_steps=20000, realtime=True,
+               progress=0.0):
+    """Drives a Server with the requests' arrival times (seconds from start);
+    progress > 0 prints a line on stderr every that many seconds."""
     srv = lbddf.Server(pool_bytes, storage=storage, k_steps=k_steps)
     pending = sorted(requests, key=lambda r: r["t"])
     ids, i = {}, 0
     t0 = time.perf_counter()
-    while i < len(pending) or any(srv.poll(rid)["state"] in ("queued", "running") for rid in ids):
+    last = 0.0
+    while True:
+        live = sum(srv.poll(rid)["state"] in ("queued", "running") for rid in ids)
+        if i >= len(pending) and live == 0:
+            break
         now = time.perf_counter() - t0
+        last = _report(progress, last, now, f"packed {storage}", len(ids) - live, len(pending))
         while i < len(pending) and (pending[i]["t"] <= now or not realtime):
             r = pending[i]
             ids[srv.submit(r["params"], r.get("fields"), tol=tol, max_steps=max_steps)] = r
@@ -67,13 +83,16 @@ def run_server(requests, pool_bytes, storage="f32", k_steps=200, tol=1e-6, max_s
     return out, srv, ids
 
 
-def run_sequential(requests, storage="f32", k_steps=200, tol=1e-6, max_steps=20000, realtime=True):
+def run_sequential(requests, storage="f32", k_steps=200, tol=1e-6, max_steps=20000, realtime=True,
+                   progress=0.0):
     """One solve at a time, first in first out, one grid per launch."""
     pending = sorted(requests, key=lambda r: r["t"])
     t0 = time.perf_counter()
     lat, states, nodes = [], [], 0.0
+    last = 0.0
     for r in pending:
         now = time.perf_counter() - t0
+        last = _report(progress, last, now, f"one at a time {storage}", len(states), len(pending))
         if realtime and r["t"] > now:
             time.sleep(r["t"] - now)
         p = dict(r["params"], storage=storage)
