@@ -804,9 +804,17 @@ __global__ __launch_bounds__(kWave * kLock<ST>) void k_step(const KArgs a, const
     run_strip<ST, BC, F, LW>(a, src, dst, bx * LW + (int)(threadIdx.x >> 6), sy, a.step);
 }
 
-// Packed step of many grids (serving): the work list holds one item per
-// wavefront strip of every resident grid; a fixed grid of wavefronts strides
-// over it.  Call i of a batch reads buffer (cur + i) & 1 of each grid.
+// Packed step of many grids (serving).  The work list holds, first, the
+// block items of the wide grids (FP32 storage, at least kWavesPerBlock tiles
+// across): a block runs kWavesPerBlock adjacent tiles of one strip in
+// lockstep, as the single-grid step does; then the wavefront items of the
+// narrow grids (all grids of the 16-bit codecs), one tile of one strip each,
+// run by the wavefronts of a block independently.  One kernel, a fixed grid of
+// blocks numbered XCD by XCD so that runs of neighbouring items share an L2,
+// goes over the list in rounds: the wide grids' items first, then the narrow
+// ones four to a block.  A grid is always wide or always narrow, so its
+// arithmetic does not depend on the mix.  Call i of a batch reads buffer
+// (cur + i) & 1 of each grid.
 struct SlotDev {
     KArgs a;
     const char *pops[2];
@@ -817,22 +825,46 @@ struct WorkItem {
     int slot, tx, sy, pad_;
 };
 
+// 3 wavefronts per SIMD: with FP32 storage the two paths together would take
+// 175 VGPRs (2 per SIMD); capped at 168 the compiler keeps two values in
+// scratch.  The 16-bit codecs have the narrow path only (measured: the wide
+// one made their packed step slower).
 template <int ST>
-__global__ __launch_bounds__(kBlock) void k_step_multi(const SlotDev *__restrict__ slots,
-                                                       const WorkItem *__restrict__ items, const int *__restrict__ nitems,
-                                                       int i) {
-    const int nw = *nitems;
-    const int waves = gridDim.x * kWavesPerBlock;
-    // the item index is the same on every lane of the wavefront: readfirstlane
-    // lets the compiler load the item and its grid's arguments with scalar
-    // loads into SGPRs instead of once per lane into VGPRs
-    const int w0 = __builtin_amdgcn_readfirstlane(blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6));
-    for (int w = w0; w < nw; w += waves) {
-        const WorkItem it = items[w];
-        const SlotDev &sd = slots[it.slot];
-        const int c = (sd.cur + i) & 1;
-        run_strip<ST, true, Dyn, 1>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]), it.tx, it.sy,
-                                    (unsigned)(sd.n + i));
+__global__ __launch_bounds__(kBlock, 3) void k_step_multi(const SlotDev *__restrict__ slots,
+                                                          const WorkItem *__restrict__ items,
+                                                          const int *__restrict__ counts, int i) {
+    const int nwide = counts[0], nnarrow = counts[1];
+    const int nblk = nwide + (nnarrow + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int wv = (int)(threadIdx.x >> 6);
+    // Rounds of gridDim.x block items; in each, the m blocks that have one
+    // take consecutive items XCD by XCD (m may be far below gridDim.x: the
+    // items must not be packed onto the first XCDs).  b is the same on every
+    // thread of the block, so both branches and the barriers in the wide one
+    // are block-uniform.
+    for (int r0 = 0; r0 < nblk; r0 += gridDim.x) {
+        const int m = min((int)gridDim.x, nblk - r0);
+        if ((int)blockIdx.x >= m) break;  // only the last round is short
+        const int b = r0 + xcd_swizzle(blockIdx.x, m);
+        if (ST == LB_STORE_F32 && b < nwide) {
+            const WorkItem it = items[b];
+            const SlotDev &sd = slots[it.slot];
+            const int c = (sd.cur + i) & 1;
+            run_strip<ST, true, Dyn, kWavesPerBlock>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]),
+                                                     it.tx + wv, it.sy, (unsigned)(sd.n + i));
+            __syncthreads();  // the next item rewrites the LDS edge slots
+        } else {
+            // the item index is the same on every lane of the wavefront:
+            // readfirstlane lets the compiler load the item and its grid's
+            // arguments with scalar loads instead of once per lane
+            const int w = __builtin_amdgcn_readfirstlane(nwide + (b - nwide) * kWavesPerBlock + wv);
+            if (w < nwide + nnarrow) {
+                const WorkItem it = items[w];
+                const SlotDev &sd = slots[it.slot];
+                const int c = (sd.cur + i) & 1;
+                run_strip<ST, true, Dyn, 1>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]), it.tx, it.sy,
+                                            (unsigned)(sd.n + i));
+            }
+        }
     }
 }
 
@@ -1530,6 +1562,18 @@ constexpr int kMaxItems = 1 << 18;
 constexpr int kMultiBlocks = 2048;  // fixed grid of the packed step: 8192 wavefronts
 constexpr int kServeStripRows = 4;   // strip height of every served grid (measured: 4 beats 8)
 
+// Work-list entries of one served grid per step: block items of
+// kWavesPerBlock tiles for a wide grid (FP32 storage only), one per tile for a
+// narrow one, times the strips.
+int grid_is_wide(const lb_params *p) {
+    return p->storage == LB_STORE_F32 && (p->nx + kTile - 1) / kTile >= kWavesPerBlock;
+}
+int work_items(const lb_params *p) {
+    const int tiles = (p->nx + kTile - 1) / kTile;
+    const int strips = (p->ny + kServeStripRows - 1) / kServeStripRows;
+    return (grid_is_wide(p) ? (tiles + kWavesPerBlock - 1) / kWavesPerBlock : tiles) * strips;
+}
+
 double now_s() {
     using namespace std::chrono;
     return duration<double>(steady_clock::now().time_since_epoch()).count();
@@ -1563,6 +1607,7 @@ struct Request {
     long max_steps = 0, steps = 0;
     int state = LBS_QUEUED, stall = 0, checks = 0, slot = -1;
     size_t off = 0, bytes = 0;
+    int items = 0;  // work-list entries per step
     double t_submit = 0, t_admit = -1, t_done = -1;
     lb_handle *h = nullptr;
     std::vector<double> result;  // 4 fields once finished
@@ -1582,12 +1627,14 @@ struct lbs_server {
     double *d_results = nullptr;
     std::vector<SlotDev> h_slots;
     std::vector<WorkItem> h_items;
+    int h_counts[2] = {0, 0};  // block items of wide grids, wavefront items of narrow ones
     std::vector<double> h_results;
     std::vector<long> slot_req;               // slot -> request id or -1
     std::map<size_t, size_t> free_blocks;     // offset -> bytes
     std::map<long, Request> reqs;
     std::deque<long> queue;
     long next_id = 1;
+    long items_resident = 0;  // work-list entries of the resident grids
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     double batches = 0, node_updates = 0, busy_s = 0, completed = 0;
@@ -1666,8 +1713,10 @@ lb_status admit(lbs_server *S) {
                 break;
             }
         if (slot < 0) return LB_OK;
+        // first in, first out: wait for room in the work list and the pool
+        if (S->items_resident + r.items > kMaxItems) return LB_OK;
         size_t off;
-        if (!pool_alloc(S, r.bytes, off)) return LB_OK;  // first in, first out: wait for memory
+        if (!pool_alloc(S, r.bytes, off)) return LB_OK;
         lb_handle *h = nullptr;
         lb_status st = lb_create(&r.p, S->pool + off, r.bytes, S->stream, &h);
         if (st != LB_OK) {
@@ -1699,6 +1748,7 @@ lb_status admit(lbs_server *S) {
         r.slot = slot;
         r.state = LBS_RUNNING;
         r.t_admit = now_s() - S->t0;
+        S->items_resident += r.items;
         S->slot_req[slot] = r.id;
         S->queue.pop_front();
     }
@@ -1717,6 +1767,7 @@ lb_status retire(lbs_server *S, Request &r, int state) {
     lb_destroy(r.h);
     r.h = nullptr;
     pool_free(S, r.off, r.bytes);
+    S->items_resident -= r.items;
     S->completed += 1;
     return st;
 }
@@ -1777,12 +1828,14 @@ lb_status lbs_submit(lbs_server *S, const lb_params *p, const double *rho, const
     if (max_steps < 1) return fail(LB_EINVAL, "max_steps must be >= 1");
     const Layout L = layout_of(p);
     if (L.total > S->pool_bytes - S->hdr) return fail(LB_ENOMEM, "request larger than the pool");
+    if (work_items(p) > kMaxItems) return fail(LB_EINVAL, "grid too large for the server's work list");
     Request r;
     r.id = S->next_id++;
     r.p = *p;
     r.tol = tol;
     r.max_steps = max_steps;
     r.bytes = L.total;
+    r.items = work_items(p);
     r.t_submit = now_s() - S->t0;
     if (rho || ux || uy || T) {
         const size_t N = (size_t)p->nx * p->ny;
@@ -1804,7 +1857,8 @@ lb_status lbs_advance(lbs_server *S, int *n_resident, int *n_queued) {
     if (!S) return fail(LB_EINVAL, "null server");
     lb_status st = admit(S);
     if (st != LB_OK) return st;
-    // work list of every resident grid
+    // work list of every resident grid: the block items of the wide grids,
+    // then the wavefront items of the narrow ones
     S->h_items.clear();
     std::vector<int> live;
     for (int slot = 0; slot < kMaxSlots; ++slot) {
@@ -1817,19 +1871,32 @@ lb_status lbs_advance(lbs_server *S, int *n_resident, int *n_queued) {
         sd.pops[1] = h->pops[1];
         sd.cur = h->cur;
         sd.n = h->n;
-        for (int sy = 0; sy < h->a.n_strips; ++sy)
-            for (int tx = 0; tx < h->a.tiles_x; ++tx) S->h_items.push_back(WorkItem{slot, tx, sy, 0});
         live.push_back(slot);
     }
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int slot : live) {
+            const Request &r = S->reqs[S->slot_req[slot]];
+            const KArgs &a = r.h->a;
+            const int wide = grid_is_wide(&r.p);
+            if (wide != (pass == 0)) continue;
+            const int step = wide ? kWavesPerBlock : 1;
+            for (int sy = 0; sy < a.n_strips; ++sy)
+                for (int tx = 0; tx < a.tiles_x; tx += step) S->h_items.push_back(WorkItem{slot, tx, sy, 0});
+        }
+        if (pass == 0) S->h_counts[0] = (int)S->h_items.size();
+    }
+    S->h_counts[1] = (int)S->h_items.size() - S->h_counts[0];
     if (n_resident) *n_resident = (int)live.size();
     if (n_queued) *n_queued = (int)S->queue.size();
     if (live.empty()) return LB_OK;
+    // admission keeps the list within kMaxItems
+    if ((long)S->h_items.size() != S->items_resident) return fail(LB_EINVAL, "work list out of step with admission");
     if ((int)S->h_items.size() > kMaxItems) return fail(LB_ENOMEM, "work list overflow");
     const double t_start = now_s();
     const int nitems = (int)S->h_items.size();
     HIPCHK(hipMemcpyAsync(S->d_slots, S->h_slots.data(), kMaxSlots * sizeof(SlotDev), hipMemcpyHostToDevice, S->stream));
     HIPCHK(hipMemcpyAsync(S->d_items, S->h_items.data(), nitems * sizeof(WorkItem), hipMemcpyHostToDevice, S->stream));
-    HIPCHK(hipMemcpyAsync(S->d_nitems, &nitems, sizeof(int), hipMemcpyHostToDevice, S->stream));
+    HIPCHK(hipMemcpyAsync(S->d_nitems, S->h_counts, 2 * sizeof(int), hipMemcpyHostToDevice, S->stream));
     HIPCHK(hipGraphLaunch(S->exec, S->stream));
     // advance the grids' clocks, then the FP64 residual of each grid in one read-back
     for (int slot : live) {

@@ -1,7 +1,8 @@
 """Continuous-batching server (lbs_*): results meet the FP32 bar against the
-oracle like the single-grid path and are bit-identical alone and in a mix;
-admission follows the pool's byte budget; a diverging request is retired
-without disturbing the others."""
+oracle like the single-grid path and are bit-identical alone and in a mix,
+for narrow grids (one wavefront per tile) and wide ones (FP32: blocks of four
+tiles in lockstep, the last group partly idle); admission follows the pool's byte
+budget; a diverging request is retired without disturbing the others."""
 import numpy as np
 import pytest
 
@@ -18,6 +19,7 @@ def _requests():
         (W.cavity(70, 1e4, 0.02, 0.02), "noise"),
         (W.cavity(66, 1e5, 1.2, 0.06, sutherland=True), "conduction"),
         (W.cavity(100, 1e3, 0.3, 0.1, sutherland=True), "conduction"),
+        (W.cavity(260, 1e4, 0.05, 0.05), "noise"),  # 5 tiles: two block items per strip
     ]
 
 
@@ -56,12 +58,12 @@ def test_server_matches_single_grid(gpu):
         assert max(e_srv) < TOL["f32"] and max(e_one) < TOL["f32"]
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_alone_and_in_the_mix_are_identical(gpu, storage):
+@pytest.mark.parametrize("storage,target", [("f32", 1), ("f16", 1), ("f32", 4), ("f16", 4)])
+def test_alone_and_in_the_mix_are_identical(gpu, storage, target):
     """Bit for bit, also with FP16 storage, whose stochastic rounding draws on
-    the node's index within its grid and the time step only."""
+    the node's index within its grid and the time step only; target 1 is a
+    narrow grid, 4 a wide one (block items with FP32 storage)."""
     reqs = _requests()
-    target = 1
     alone = lbddf.Server(_pool(reqs), storage=storage, k_steps=50)
     a = alone.submit(reqs[target][0], _fields(*reqs[target]), tol=0.0, max_steps=400)
     _run_to_end(alone)
@@ -76,7 +78,7 @@ def test_alone_and_in_the_mix_are_identical(gpu, storage):
 def test_admission_follows_the_byte_budget(gpu):
     reqs = _requests()
     biggest = max(lbddf.state_bytes(p) for p, _ in reqs)
-    # room for the two largest at once (or a few smaller ones), not for all eight
+    # room for the two largest at once (or a few smaller ones), not for all of them
     pool = lbddf.load().lbs_pool_overhead() + 2 * (biggest + 256)
     srv = lbddf.Server(pool, k_steps=100)
     ids = [srv.submit(p, _fields(p, k), tol=0.0, max_steps=300) for p, k in reqs * 2]
@@ -87,9 +89,10 @@ def test_admission_follows_the_byte_budget(gpu):
         saw_queue |= q > 0
         if r == 0 and q == 0:
             break
-    footprints = sorted(lbddf.state_bytes(p) + 256 for p, _ in reqs)
+    # the most grids that can be resident at once: the smallest of all submitted
+    footprints = sorted(lbddf.state_bytes(p) + 256 for p, _ in reqs * 2)
     fit = max(n for n in range(1, len(footprints) + 1) if sum(footprints[:n]) <= pool - lbddf.load().lbs_pool_overhead())
-    assert saw_queue and 1 <= max_res <= fit < 8
+    assert saw_queue and 1 <= max_res <= fit < 2 * len(reqs)
     assert all(srv.poll(i)["state"] == "step_cap" for i in ids)
     st = srv.stats()
     assert st["free_bytes"] == pool - lbddf.load().lbs_pool_overhead() - (pool - lbddf.load().lbs_pool_overhead()) % 256
