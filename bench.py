@@ -119,8 +119,15 @@ def cpu_baseline(seconds: float):
         steps += 2
     t = time.perf_counter() - t0
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            cpu = next(line.split(":", 1)[1].strip() for line in fh if line.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return dict(value=n * n * steps / t / 1e6, unit="MLUPS", cores=cores, kind="oracle",
-                sample=f"periodic {n}x{n}, same recipe, {steps} steps in {t:.1f} s (FP64, OpenMP over rows)")
+                sample=f"periodic {n}x{n}, same recipe, {steps} steps in {t:.1f} s (FP64, OpenMP over rows)",
+                cpu=cpu)
 
 
 def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 200, tol: float = 1e-8,

@@ -187,8 +187,10 @@ const char *lb_last_error(void);
  *
  * The caller hands the server one device pool; the server keeps the state of
  * every admitted request resident in it and admits queued requests first in,
- * first out as their byte footprint (lb_state_bytes) and a slot (at most 512
- * resident grids) become free.  One lbs_advance call runs k steps of every
+ * first out as their byte footprint (lb_state_bytes), a slot (at most 512
+ * resident grids) and room in the packed kernel's work list (2^18 items: one
+ * per 4 rows of each 64-column tile, or of each group of four tiles for FP32
+ * grids at least 256 columns wide) become free.  One lbs_advance call runs k steps of every
  * resident grid as a hipGraph of k launches of one packed kernel (the same
  * per-node step as lb_step), then reads every grid's FP64 convergence
  * residual r = ||T - T_snap|| / ||T|| (snapshot k steps earlier; the first
@@ -220,7 +222,8 @@ size_t lbs_pool_overhead(void);
 lb_status lbs_create(void *dev_pool, size_t pool_bytes, int storage, int k_steps, void *hip_stream, lbs_server **out);
 
 /* Queues a request (host fields as in lb_init, NULL: rest state); *id
- * receives its handle.  LB_ENOMEM when it cannot fit the pool at all. */
+ * receives its handle.  LB_ENOMEM when it cannot fit the pool at all,
+ * LB_EINVAL when its work items alone exceed the work list. */
 lb_status lbs_submit(lbs_server *s, const lb_params *p, const double *rho, const double *ux, const double *uy,
                      const double *T, double tol, long max_steps, long *id);
 
