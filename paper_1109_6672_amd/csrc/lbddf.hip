@@ -170,7 +170,10 @@ template <> struct Codec<LB_STORE_F16> {
     static __device__ __forceinline__ float ld(const Planes &P, unsigned vo, int q) {
         const Rsrc r = q < 9 ? P.f : P.h;
         const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, (q % 9) * P.pb, 0);
-        return (float)__builtin_bit_cast(_Float16, b) * (1.f / f16_scale(q));
+        // an FMA with a zero addend, not a product: it becomes one mixed-
+        // precision FMA that converts and scales (a product of a converted
+        // value stays two instructions when it has several users)
+        return __builtin_fmaf((float)__builtin_bit_cast(_Float16, b), 1.f / f16_scale(q), 0.f);
     }
     // rb: random bits; the conversion rounds stochastically (gfx950's
     // v_cvt_sr_f16_f32 adds the high bits of rb below the kept mantissa of the
@@ -1147,14 +1150,17 @@ void set_strip(lb_handle *h) {
     int R = h->strip_user;
     if (R <= 0) {
         // 8-row strips for FP32 storage, 16 for the 16-bit codecs (measured
-        // best on 8192^2 and 4096^2); shorter ones, down to 1 row, while the
-        // grid would give fewer than 2048 wavefronts, 8 per CU (measured on
-        // 512^2 and 2048 x 256 in FP32 and FP16)
+        // best on 8192^2, 4096^2 and 2048^2); shorter ones, down to 1 row,
+        // while the grid would give fewer wavefronts than a floor: 4096 (16
+        // per CU) for fully periodic grids, 2048 for bounded ones, whose step
+        // is heavier (measured on periodic 1024^2, the 512^2 cavity and the
+        // 2048 x 256 channel in FP32 and FP16)
         const bool f32 = h->p.storage == LB_STORE_F32;
         const int lw = f32 ? kLock<LB_STORE_F32> : kLock<LB_STORE_F16>;
         const long long bcols = (a.tiles_x + lw - 1) / lw;
+        const long long floor_waves = (a.per_x && a.per_y) ? 4096 : 2048;
         R = f32 ? 8 : 16;
-        while (R > 1 && bcols * lw * ((a.ny + R - 1) / R) < 2048) R >>= 1;
+        while (R > 1 && bcols * lw * ((a.ny + R - 1) / R) < floor_waves) R >>= 1;
     }
     a.strip_rows = R;
     a.n_strips = (a.ny + R - 1) / R;
