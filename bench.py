@@ -167,6 +167,44 @@ def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 2
     return out
 
 
+def pmc_summary(run_dir: str, n: int = 8192) -> dict:
+    """HBM bytes per launch of the headline step from rocprofv3 PMC runs under
+    run_dir ({f32,f16}fetch and {f32,f16}write with FETCH_SIZE / WRITE_SIZE,
+    cfetch and cwrite on --copy-only).  The scales come from the copy: bytes it
+    moved over the KiB each counter reports for it.  Returns the entries of
+    profiles/traffic.json for the current device code."""
+    import csv
+
+    def values(sub, counter, match):
+        with open(os.path.join(run_dir, sub, "c_counter_collection.csv")) as fh:
+            return [float(r["Counter_Value"]) for r in csv.DictReader(fh)
+                    if r["Counter_Name"] == counter and match(r["Kernel_Name"])]
+
+    def mean(v):
+        if not v:
+            raise ValueError("no matching dispatches")
+        return sum(v) / len(v)
+
+    copy = lambda k: "copyBuffer" in k
+    copied_kib = 2 * 2**30 / 1024  # --copy-only copies 2 GiB
+    fetch_scale = round(copied_kib / mean(values("cfetch", "FETCH_SIZE", copy)), 2)
+    write_scale = round(copied_kib / mean(values("cwrite", "WRITE_SIZE", copy)), 2)
+    sha, out = kernel_source_hash(), {}
+    for st, code in (("f32", 0), ("f16", 1)):
+        step = lambda k, code=code: f"k_step<{code}, false" in k
+        f = mean(values(f"{st}fetch", "FETCH_SIZE", step))
+        w = mean(values(f"{st}write", "WRITE_SIZE", step))
+        out[f"lb_step_periodic{n}_{st}"] = dict(
+            kernel=f"k_step<{st.upper()}, periodic> (void (anonymous namespace)::k_step<{code}, false, "
+                   "(anonymous namespace)::Head>)",
+            kernel_source_sha=sha, fetch_kib_per_launch_raw=round(f, 1), write_kib_per_launch_raw=round(w, 1),
+            fetch_scale=fetch_scale, write_scale=write_scale,
+            bytes_per_launch=int(round(1024 * (f * fetch_scale + w * write_scale))),
+            algorithmic_bytes_per_launch=BYTES_PER_NODE[st] * n * n,
+            source=f"profiles/lb_step_periodic{n}_{st}.md")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -187,7 +225,16 @@ def main():
     ap.add_argument("--only", default="", help="storage of a single run (profiling): f32 | f16 | bf16")
     ap.add_argument("--copy-only", action="store_true",
                     help="HBM counter calibration: 5 plain device copies of 2 GiB (torch copy kernel)")
+    ap.add_argument("--pmc-summary", metavar="DIR", default="",
+                    help="no GPU: write profiles/traffic.json from the rocprofv3 PMC runs under DIR")
     args = ap.parse_args()
+    if args.pmc_summary:
+        t = pmc_summary(args.pmc_summary, args.n)
+        with open(os.path.join(ROOT, "profiles", "traffic.json"), "w") as fh:
+            json.dump(t, fh, indent=2)
+            fh.write("\n")
+        print(json.dumps(t, indent=2))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU halo-exchange design is described, not built).", file=sys.stderr)

@@ -39,3 +39,32 @@ def test_traffic_is_reported_only_for_the_profiled_device_code():
     got = bench.measured_traffic(key, 8192 * 8192)
     assert got == (t[key]["bytes_per_launch"] if t[key]["kernel_source_sha"] == h else None)
     assert bench.measured_traffic("no such workload", 1) is None
+
+
+def _csv(path, rows):
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "c_counter_collection.csv"), "w") as fh:
+        fh.write('"Dispatch_Id","Kernel_Name","Counter_Name","Counter_Value"\n')
+        for i, (k, c, v) in enumerate(rows):
+            fh.write(f'{i},"{k}","{c}",{v}\n')
+
+
+def test_pmc_summary_scales_the_counters_by_the_copy(tmp_path):
+    """A copy of 2 GiB that FETCH_SIZE reports as 1 GiB gives a read scale of
+    2; the step's bytes are then 2 x fetch + 1 x write, in KiB x 1024."""
+    d = str(tmp_path)
+    copy = "__amd_rocclr_copyBuffer"
+    _csv(os.path.join(d, "cfetch"), [(copy, "FETCH_SIZE", 1048576.0)] * 3 + [("fill", "FETCH_SIZE", 5.0)])
+    _csv(os.path.join(d, "cwrite"), [(copy, "WRITE_SIZE", 2097152.0)] * 3)
+    for st, code in (("f32", 0), ("f16", 1)):
+        k = f"void (anonymous namespace)::k_step<{code}, false, (anonymous namespace)::Head>(...)"
+        _csv(os.path.join(d, f"{st}fetch"), [(k, "FETCH_SIZE", 100.0), (k, "FETCH_SIZE", 300.0),
+                                            ("k_init", "FETCH_SIZE", 9e9)])
+        _csv(os.path.join(d, f"{st}write"), [(k, "WRITE_SIZE", 50.0)])
+    t = bench.pmc_summary(d, n=64)
+    e = t["lb_step_periodic64_f32"]
+    assert e["fetch_scale"] == 2.0 and e["write_scale"] == 1.0
+    assert e["bytes_per_launch"] == 1024 * (200.0 * 2 + 50.0)
+    assert e["algorithmic_bytes_per_launch"] == 144 * 64 * 64
+    assert t["lb_step_periodic64_f16"]["algorithmic_bytes_per_launch"] == 72 * 64 * 64
+    assert e["kernel_source_sha"] == bench.kernel_source_hash()
