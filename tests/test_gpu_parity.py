@@ -107,6 +107,51 @@ def test_channel_inlet_outlet(gpu):
     _check(e, "f32")
 
 
+@pytest.mark.parametrize("nx,ny", [(1, 1), (1, 5), (7, 1), (2, 3), (65, 1), (64, 2), (3, 130)])
+def test_degenerate_periodic_grids(gpu, nx, ny):
+    """Grids narrower than a tile, one row or one node: the periodic wrap folds
+    every neighbour back onto the grid, one strip covers it all."""
+    p = W.periodic(nx, ny)
+    _, _, _, _, e = run_pair(p, W.gaussian_fields(p, sigma=1e-3), 50, "degenerate periodic")
+    _check(e, "f32")
+
+
+@pytest.mark.parametrize("case", ["couette 1x3", "couette 4x3", "adiabatic couette 2x4", "cavity 4x4",
+                                  "cavity 5x5", "channel 3x1", "channel 5x2"])
+def test_smallest_bounded_grids(gpu, case):
+    """The smallest grids the library accepts with walls (3 nodes across a
+    Dirichlet pair, 4 with an adiabatic side) or an inlet and an outlet (3
+    columns): almost every node is a boundary node.  The cavities have hot and
+    cold side walls, an adiabatic floor and an adiabatic lid moving at 0.05,
+    and no gravity: a buoyant flow in a 5 x 5 box moves at ~3e-4, where the
+    FP32 floor of stratified deviations (~5e-9 in u) would be what is
+    measured, not the boundary code."""
+    kind, shape = case.rsplit(" ", 1)
+    nx, ny = (int(v) for v in shape.split("x"))
+    if kind == "couette":
+        p, f = W.couette(nx=nx, ny=ny), None
+    elif kind == "adiabatic couette":
+        p, f = W.couette_paper(1.0, 0.35, nx=nx, ny=ny), None
+    elif kind == "cavity":
+        p = W.cavity(nx, 100.0, 0.02, 0.01)
+        p["g"] = 0.0
+        p["sides"][3] = W.side("adiabatic", 0.05, 0.0, 1.0)
+        f = W.noisy_temperature_fields(p)
+    else:
+        p, f = W.channel(nx=nx, ny=ny, period=20.0), None
+    _, _, _, _, e = run_pair(p, f if f is not None else W.rest_fields(p), 100, f"smallest {case}")
+    _check(e, "f32")
+
+
+def test_zero_steps_change_nothing(gpu):
+    p = W.periodic(70, 33)
+    s = lbddf.Solver(p).init(*W.gaussian_fields(p, sigma=1e-3))
+    before = s.populations()
+    s.step(0)
+    assert s.time == 0
+    np.testing.assert_array_equal(s.populations(), before)
+
+
 def test_deterministic_and_strip_invariant(gpu):
     """Bitwise identical results for repeated runs and for any strip height."""
     p = W.cavity(70, 1e4, 0.2, 0.05)
