@@ -198,7 +198,8 @@ const char *lb_last_error(void);
  * at admission) in one copy,
  * retires grids that converged (r < tol), reached a plateau (r below 1e-3 of
  * its largest value and no new minimum for max(10, n/2) of its n checks so
- * far, minima counted from that maximum), hit max_steps or became unstable,
+ * far, minima counted from that maximum), reached max_steps (checked after
+ * each batch, so a request runs to the next multiple of k) or became unstable,
  * stores their final fields on the host, frees their memory and admits
  * waiting requests.
  * Requests of one server share its storage type; inlet sides are not served.
