@@ -170,7 +170,7 @@ def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 2
 def pmc_summary(run_dir: str, n: int = 8192) -> dict:
     """HBM bytes per launch of the headline step from rocprofv3 PMC runs under
     run_dir ({f32,f16}fetch and {f32,f16}write with FETCH_SIZE / WRITE_SIZE,
-    cfetch and cwrite on --copy-only).  The scales come from the copy: bytes it
+    the FP16 pair optional; cfetch and cwrite on --copy-only).  The scales come from the copy: bytes it
     moved over the KiB each counter reports for it.  Returns the entries of
     profiles/traffic.json for the current device code."""
     import csv
@@ -191,6 +191,8 @@ def pmc_summary(run_dir: str, n: int = 8192) -> dict:
     write_scale = round(copied_kib / mean(values("cwrite", "WRITE_SIZE", copy)), 2)
     sha, out = kernel_source_hash(), {}
     for st, code in (("f32", 0), ("f16", 1)):
+        if st != "f32" and not os.path.isdir(os.path.join(run_dir, f"{st}fetch")):
+            continue  # the FP16 runs are optional
         step = lambda k, code=code: f"k_step<{code}, false" in k
         f = mean(values(f"{st}fetch", "FETCH_SIZE", step))
         w = mean(values(f"{st}write", "WRITE_SIZE", step))
