@@ -95,6 +95,38 @@ def test_small_dT_cavity_reproduces_table_ii():
         assert abs(m[k] - row[k]) < 0.02, (k, m[k], row[k])
 
 
+@pytest.mark.parametrize("Ra,n,mu_r,cap", [(1e3, 101, 0.05, 1_000_000), (1e5, 201, 0.02, 4_000_000)])
+def test_small_dT_cavity_table_ii_other_rows(Ra, n, mu_r, cap):
+    """The Ra = 1e3 and 1e5 rows of Table II on the paper's grids (100 and 200
+    cells, H = n - 1), run to convergence (Ra = 1e5 stops on the plateau test
+    near r = 3e-8 after about 3.3 million steps).  The paper's table is the
+    Boussinesq limit, which a compressible model approaches as the
+    stratification g H / (R T0) shrinks: 0.053 at Ra = 1e3 (mu_r = 0.05),
+    0.21 at Ra = 1e5 (mu_r = 0.02; smaller mu_r, tau_f = 0.53 or 0.545,
+    diverges within 10,000 steps here, with or without untied bulk rates or a
+    conduction start).  At Ra = 1e5, u_max is held to 4 %: the paper's value
+    and its two references already spread by 3 % for that quantity."""
+    with open(os.path.join(HERE, "golden", "table2_cavity.json")) as fh:
+        tab = json.load(fh)
+    row = dict(zip(tab["columns"], next(r for r in tab["rows"] if r[0] == Ra)))
+    p = W.cavity(n, Ra, 0.02, mu_r)
+    print(f"[case] Table II Ra={Ra:g} cavity {n}x{n} tau_f={3 * mu_r + 0.5:.2f} g={p['g']:.4e}", flush=True)
+    s = lbddf.Solver(p).init(*W.noisy_temperature_fields(p))
+    state, r = _converge(s, check=2000, cap=cap)
+    rho, ux, uy, T = s.macros()
+    m = P.cavity_metrics(p, ux, uy, T)
+    print(f"       {state} after {s.time} steps (r = {r:.2e}): " + ", ".join(f"{k} {v:.4f}" for k, v in m.items()),
+          flush=True)
+    print("       paper: " + ", ".join(f"{k} {row[k]:.4f}" for k in ("Nu", "u_max", "y_max", "v_max", "x_max")),
+          flush=True)
+    assert state != "step_cap" and s.diag()["bad"] == 0
+    for k in ("Nu", "u_max", "v_max"):
+        bar = 0.04 if (Ra >= 1e5 and k == "u_max") else 0.02
+        assert abs(m[k] / row[k] - 1) < bar, (k, m[k], row[k])
+    for k in ("y_max", "x_max"):
+        assert abs(m[k] - row[k]) < 2.0 / (n - 1) + 1e-9, (k, m[k], row[k])
+
+
 def test_small_dT_cavity_converged_state_against_the_oracle():
     """Config 2 run 268,000 steps (its convergence above) on the GPU and in the
     FP64 oracle.  rho and T meet the FP32 bar and the Table II quantities agree
