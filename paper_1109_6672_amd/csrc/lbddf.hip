@@ -964,7 +964,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(const KArgs a, const char *__re
         const int x = i % a.nx, y = i / a.nx;
         float d[18];
         Mom m;
-        node_state<ST, BC>(a, planes(src, a), x, y, d, m);
+        node_state<ST, BC>(a, P, x, y, d, m);
         double sf = 0, sh = 0;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
