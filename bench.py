@@ -64,7 +64,7 @@ def bounded_case(kind: str, storage: str):
     return p, W.rest_fields(p)
 
 
-def time_gpu(n: int, storage: str, steps: int, warmup: int, strip_rows: int = 0, case=None):
+def time_gpu(n: int, storage: str, steps: int, warmup: int, strip_rows: int = 0, case=None, arith: str = "f32"):
     import torch
 
     from paper_1109_6672_amd import lbddf, workloads as W
@@ -75,7 +75,7 @@ def time_gpu(n: int, storage: str, steps: int, warmup: int, strip_rows: int = 0,
     else:
         p, fields = bounded_case(case, storage)
     n_nodes = p["nx"] * p["ny"]
-    s = lbddf.Solver(p, device=0)
+    s = lbddf.Solver(p, device=0, arith=arith)
     s.init(*fields)
     del fields
     if strip_rows:
@@ -281,6 +281,10 @@ def main():
             r = time_gpu(n, storage, args.steps, args.warmup)
             extra[f"{storage}_{n}"] = {k: r[k] for k in ("mlups", "gbs", "ms_per_step", "strip_rows")}
             print(f"# {storage} {n}^2: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
+        # the library with the step's arithmetic in FP64 (FP32 storage)
+        r = time_gpu(args.n, "f32", args.steps, args.warmup, arith="f64")
+        extra[f"f32_{args.n}_fp64_arith"] = {k: r[k] for k in ("mlups", "gbs", "ms_per_step", "strip_rows")}
+        print(f"# f32 storage, FP64 arithmetic {args.n}^2: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         for case, storage in (("cavity512", "f32"), ("cavity512", "f16"), ("channel2048x256", "f32")):
             r = time_gpu(0, storage, args.steps, args.warmup, case=case)
             extra[f"{storage}_{case}"] = {k: r[k] for k in ("mlups", "gbs", "ms_per_step", "strip_rows")}

@@ -18,17 +18,28 @@ HIPCC_FLAGS = [
 ]
 
 
-def build(verbose: bool = False) -> str:
-    tmp = OUT + ".tmp"
-    cmd = ["hipcc", *HIPCC_FLAGS, "-o", tmp, *SOURCES]
+OUT_FP64 = os.path.join(HERE, "liblbddf_fp64.so")  # the step's arithmetic in FP64
+
+
+def _compile(out: str, extra: list, verbose: bool) -> str:
+    tmp = out + ".tmp"
+    cmd = ["hipcc", *HIPCC_FLAGS, *extra, "-o", tmp, *SOURCES]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed for liblbddf.so")
+        raise RuntimeError(f"hipcc failed for {os.path.basename(out)}")
     if verbose:
         sys.stderr.write(r.stderr)
-    os.replace(tmp, OUT)
-    return OUT
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    """Both libraries from the one source: FP32 arithmetic (liblbddf.so) and
+    FP64 arithmetic (liblbddf_fp64.so, -DLB_ARITH_FP64); the same ABI and
+    storage formats.  Returns the path of the FP32 one."""
+    _compile(OUT_FP64, ["-DLB_ARITH_FP64"], verbose)
+    return _compile(OUT, [], verbose)
 
 
 if __name__ == "__main__":

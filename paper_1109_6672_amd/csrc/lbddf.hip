@@ -50,6 +50,14 @@
 
 #include "lbddf.h"
 
+// Arithmetic type of the step: FP32, or FP64 in the library built with
+// LB_ARITH_FP64 (liblbddf_fp64.so: same ABI and storage formats).
+#ifdef LB_ARITH_FP64
+typedef double real;
+#else
+typedef float real;
+#endif
+
 namespace {
 
 constexpr int kWave = 64;
@@ -75,17 +83,17 @@ struct KArgs {
     long long plane_bytes;  // a half (f or h) spans 9 plane_bytes
     unsigned pstride;       // bytes from one population's row to the next one's
     int total, heat, corr, coupled, bgk, visc, rho_press, has_force;
-    float rho0, E0, inv_E0, half_g, g, Pr;
+    real rho0, E0, inv_E0, half_g, g, Pr;
     // relaxation for a constant tau_f
-    float s_nu, s_e, s_z, s_q, s_rho, s_j, omega_h, kcoup;
+    real s_nu, s_e, s_z, s_q, s_rho, s_j, omega_h, kcoup;
     int tie_e, tie_z;
     // viscosity laws: mu3 = 3 mu_ref, r = cT theta = T / T_ref
-    float mu3, cT, visc_n, sT;
+    real mu3, cT, visc_n, sT;
     // sides x-, x+, y-, y+
     int side_kind[4];
-    float side_ux[4], side_uy[4], side_dth[4];
+    real side_ux[4], side_uy[4], side_dth[4];
     // inlet state and time step of the launch
-    float in_drho, in_ux, in_dth;
+    real in_drho, in_ux, in_dth;
     unsigned step;
 };
 
@@ -111,10 +119,28 @@ struct Head {
 #define F_BGK (F::fixed ? F::bgk : (bool)a.bgk)
 #define F_CTAU (F::fixed ? F::ctau : (a.visc == LB_VISC_CONST_TAU))
 
-__device__ __forceinline__ float frcp(float x) {
-    const float r = __builtin_amdgcn_rcpf(x);
-    return fmaf(r, fmaf(-x, r, 1.f), r);
+#ifndef LB_ARITH_FP64
+__device__ __forceinline__ real frcp(real x) {
+    const real r = __builtin_amdgcn_rcpf(x);
+    return fma(r, fma(-x, r, real(1.)), r);
 }
+#else
+__device__ __forceinline__ real frcp(real x) { return real(1.) / x; }
+#endif
+
+// readlane of a real (two 32-bit halves in FP64)
+#ifndef LB_ARITH_FP64
+__device__ __forceinline__ real readlane_real(real v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+#else
+__device__ __forceinline__ real readlane_real(real v, int lane) {
+    const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, lane);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), lane);
+    return __builtin_bit_cast(real, ((unsigned long long)hi << 32) | lo);
+}
+#endif
 
 // ------------------------------------------------------------------ storage
 // A population buffer is addressed through two raw buffer resources, one for
@@ -148,57 +174,57 @@ typedef __bf16 B2 __attribute__((ext_vector_type(2)));
 template <int ST> struct Codec;
 template <> struct Codec<LB_STORE_F32> {
     static constexpr unsigned bytes = 4;
-    static __device__ __forceinline__ float ld(const Planes &P, unsigned vo, int q) {
+    static __device__ __forceinline__ real ld(const Planes &P, unsigned vo, int q) {
         const Rsrc r = q < 9 ? P.f : P.h;
-        return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, (q % 9) * P.pb, 0));
+        return (real)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, (q % 9) * P.pb, 0));
     }
-    static __device__ __forceinline__ void st(const Planes &P, unsigned vo, float v, int q, unsigned) {
+    static __device__ __forceinline__ void st(const Planes &P, unsigned vo, real v, int q, unsigned) {
         const Rsrc r = q < 9 ? P.f : P.h;
-        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, vo, (q % 9) * P.pb, kNT);
+        __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)v), r, vo, (q % 9) * P.pb, kNT);
     }
 };
 // FP16 keeps deviation * 2^(8 + k_a), k_a = 1, 3, 5 for the rest, axis and
 // diagonal velocities (about 1 / w_a): every plane then spans the same
 // range, far above the FP16 subnormals and far below its maximum.  Powers of
 // two make the scaling exact.
-__device__ __forceinline__ float f16_scale(int q) {
+__device__ __forceinline__ real f16_scale(int q) {
     const int a = q % 9;
-    return a == 0 ? 512.f : (a < 5 ? 2048.f : 8192.f);
+    return a == 0 ? real(512.) : (a < 5 ? real(2048.) : real(8192.));
 }
 template <> struct Codec<LB_STORE_F16> {
     static constexpr unsigned bytes = 2;
-    static __device__ __forceinline__ float ld(const Planes &P, unsigned vo, int q) {
+    static __device__ __forceinline__ real ld(const Planes &P, unsigned vo, int q) {
         const Rsrc r = q < 9 ? P.f : P.h;
         const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, (q % 9) * P.pb, 0);
         // an FMA with a zero addend, not a product: it becomes one mixed-
         // precision FMA that converts and scales (a product of a converted
         // value stays two instructions when it has several users)
-        return __builtin_fmaf((float)__builtin_bit_cast(_Float16, b), 1.f / f16_scale(q), 0.f);
+        return fma((real)__builtin_bit_cast(_Float16, b), real(1.) / f16_scale(q), real(0.));
     }
     // rb: random bits; the conversion rounds stochastically (gfx950's
     // v_cvt_sr_f16_f32 adds the high bits of rb below the kept mantissa of the
     // magnitude, then truncates), which leaves no systematic rounding bias in
     // steady flows.
-    static __device__ __forceinline__ void st(const Planes &P, unsigned vo, float v, int q, unsigned rb) {
+    static __device__ __forceinline__ void st(const Planes &P, unsigned vo, real v, int q, unsigned rb) {
         const Rsrc r = q < 9 ? P.f : P.h;
         // the conversion writes one half of a register; the other half is
         // never stored, so the input's own register serves as the old value
-        const float sv = v * f16_scale(q);
+        const float sv = (float)(v * f16_scale(q));
         const H2 h = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(H2, sv), sv, rb, false);
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), r, vo, (q % 9) * P.pb, kNT);
     }
 };
 template <> struct Codec<LB_STORE_BF16> {
     static constexpr unsigned bytes = 2;
-    static __device__ __forceinline__ float ld(const Planes &P, unsigned vo, int q) {
+    static __device__ __forceinline__ real ld(const Planes &P, unsigned vo, int q) {
         const Rsrc r = q < 9 ? P.f : P.h;
         const unsigned short b = __builtin_amdgcn_raw_buffer_load_b16(r, vo, (q % 9) * P.pb, 0);
         return __uint_as_float(((unsigned)b) << 16);
     }
     // stochastic rounding of the 16 dropped mantissa bits (see the FP16 codec)
-    static __device__ __forceinline__ void st(const Planes &P, unsigned vo, float v, int q, unsigned rb) {
+    static __device__ __forceinline__ void st(const Planes &P, unsigned vo, real v, int q, unsigned rb) {
         const Rsrc r = q < 9 ? P.f : P.h;
-        const B2 h = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(B2, v), v, rb, false);
+        const B2 h = __builtin_amdgcn_cvt_sr_bf16_f32(__builtin_bit_cast(B2, (float)v), (float)v, rb, false);
         __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, h[0]), r, vo, (q % 9) * P.pb, kNT);
     }
 };
@@ -209,14 +235,14 @@ template <> struct Codec<LB_STORE_BF16> {
 // (possibly rebuilt) populations, which equal drho, jx and jy + rho g / 2 on
 // interior nodes.
 struct Mom {
-    float drho, rho, jx, jy, ux, uy, dth, sf, sx, sy;
+    real drho, rho, jx, jy, ux, uy, dth, sf, sx, sy;
 };
 
 // Pull-gather (Eq. 45): population a of node (x, y) is the post-collision
 // value stored at (x, y) - e_a, with periodic wrap.  Sources of a bounded
 // axis are interior nodes, so their neighbours never leave the domain.
 template <int ST>
-__device__ __forceinline__ void gather(const KArgs &a, const Planes &S, int x, int y, float d[18]) {
+__device__ __forceinline__ void gather(const KArgs &a, const Planes &S, int x, int y, real d[18]) {
     int xm = x - 1, xp = x + 1, ym = y - 1, yp = y + 1;
     xm += (xm < 0) ? a.nx : 0;
     xp -= (xp >= a.nx) ? a.nx : 0;
@@ -236,25 +262,25 @@ __device__ __forceinline__ void gather(const KArgs &a, const Planes &S, int x, i
 // Eq. 46 with the forcing note (rho u = sum e f + a/2, a = (0, -rho g)) and
 // Eq. 37 / the internal-energy form, written for deviations from rest.
 template <class F>
-__device__ __forceinline__ Mom moments(const KArgs &a, const float d[18]) {
+__device__ __forceinline__ Mom moments(const KArgs &a, const real d[18]) {
     Mom m;
-    const float s1 = (d[1] + d[3]) + (d[2] + d[4]);
-    const float s2 = (d[5] + d[7]) + (d[6] + d[8]);
+    const real s1 = (d[1] + d[3]) + (d[2] + d[4]);
+    const real s2 = (d[5] + d[7]) + (d[6] + d[8]);
     m.drho = d[0] + (s1 + s2);
-    const float jx = (d[1] - d[3]) + (d[5] - d[7]) + (d[8] - d[6]);
-    const float jy = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
+    const real jx = (d[1] - d[3]) + (d[5] - d[7]) + (d[8] - d[6]);
+    const real jy = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
     m.sf = m.drho;
     m.sx = jx;
     m.sy = jy;
     m.rho = a.rho0 + m.drho;
-    const float ir = frcp(m.rho);
+    const real ir = frcp(m.rho);
     m.jx = jx;
     m.jy = F_FORCE ? jy - a.half_g * m.rho : jy;
     m.ux = m.jx * ir;
     m.uy = m.jy * ir;
-    const float sh = ((d[9] + d[10]) + (d[11] + d[12])) + ((d[13] + d[14]) + (d[15] + d[16])) + d[17];
-    const float e = (sh - m.drho * a.E0) * ir;  // E - E0 (total) or (rho E_int - rho E0)/rho
-    m.dth = F_TOTAL ? (e - 0.5f * (m.ux * m.ux + m.uy * m.uy)) * a.inv_E0 : e * a.inv_E0;
+    const real sh = ((d[9] + d[10]) + (d[11] + d[12])) + ((d[13] + d[14]) + (d[15] + d[16])) + d[17];
+    const real e = (sh - m.drho * a.E0) * ir;  // E - E0 (total) or (rho E_int - rho E0)/rho
+    m.dth = F_TOTAL ? (e - real(0.5) * (m.ux * m.ux + m.uy * m.uy)) * a.inv_E0 : e * a.inv_E0;
     return m;
 }
 
@@ -264,46 +290,46 @@ __device__ __forceinline__ Mom moments(const KArgs &a, const float d[18]) {
 //   f_eq - f_rest = w [drho + c rho th - 1.5 j.u + (e.j)(B + 4.5 e.u)],
 //   c = -1, 1/2, 2 and B = 3, 3 - 1.5 th, 3 + 3 th for |e|^2 = 0, 1, 2.
 template <class F>
-__device__ __forceinline__ void equilibria(const KArgs &a, const Mom &m, float fe[9], float he[9]) {
-    const float w0 = 4.f / 9.f, w1 = 1.f / 9.f, w2 = 1.f / 36.f;
-    const float th = F_COUPLED ? m.dth : 0.f;  // theta_eq - 1
-    const float ux = m.ux, uy = m.uy, jx = m.jx, jy = m.jy, drho = m.drho, rho = m.rho;
-    const float ju = jx * ux + jy * uy;
-    const float base = drho - 1.5f * ju;
-    const float rth = rho * th;
-    const float A0 = base - rth, A1 = base + 0.5f * rth, A2 = base + 2.f * rth;
-    const float B1 = 3.f - 1.5f * th, B2 = 3.f + 3.f * th;
-    const float v5 = ux + uy, v6 = uy - ux, j5 = jx + jy, j6 = jy - jx;
+__device__ __forceinline__ void equilibria(const KArgs &a, const Mom &m, real fe[9], real he[9]) {
+    const real w0 = real(4.) / real(9.), w1 = real(1.) / real(9.), w2 = real(1.) / real(36.);
+    const real th = F_COUPLED ? m.dth : real(0.);  // theta_eq - 1
+    const real ux = m.ux, uy = m.uy, jx = m.jx, jy = m.jy, drho = m.drho, rho = m.rho;
+    const real ju = jx * ux + jy * uy;
+    const real base = drho - real(1.5) * ju;
+    const real rth = rho * th;
+    const real A0 = base - rth, A1 = base + real(0.5) * rth, A2 = base + real(2.) * rth;
+    const real B1 = real(3.) - real(1.5) * th, B2 = real(3.) + real(3.) * th;
+    const real v5 = ux + uy, v6 = uy - ux, j5 = jx + jy, j6 = jy - jx;
     fe[0] = w0 * A0;
-    fe[1] = w1 * (A1 + jx * (B1 + 4.5f * ux));
-    fe[3] = w1 * (A1 - jx * (B1 - 4.5f * ux));
-    fe[2] = w1 * (A1 + jy * (B1 + 4.5f * uy));
-    fe[4] = w1 * (A1 - jy * (B1 - 4.5f * uy));
-    fe[5] = w2 * (A2 + j5 * (B2 + 4.5f * v5));
-    fe[7] = w2 * (A2 - j5 * (B2 - 4.5f * v5));
-    fe[6] = w2 * (A2 + j6 * (B2 + 4.5f * v6));
-    fe[8] = w2 * (A2 - j6 * (B2 - 4.5f * v6));
-    const float u2 = ux * ux + uy * uy;
+    fe[1] = w1 * (A1 + jx * (B1 + real(4.5) * ux));
+    fe[3] = w1 * (A1 - jx * (B1 - real(4.5) * ux));
+    fe[2] = w1 * (A1 + jy * (B1 + real(4.5) * uy));
+    fe[4] = w1 * (A1 - jy * (B1 - real(4.5) * uy));
+    fe[5] = w2 * (A2 + j5 * (B2 + real(4.5) * v5));
+    fe[7] = w2 * (A2 - j5 * (B2 - real(4.5) * v5));
+    fe[6] = w2 * (A2 + j6 * (B2 + real(4.5) * v6));
+    fe[8] = w2 * (A2 - j6 * (B2 - real(4.5) * v6));
+    const real u2 = ux * ux + uy * uy;
     if (F_TOTAL) {
         // h_eq - h_rest = w [rho0 (E - E0) + c (p theta - p0) + p (3 eu + 9 eu^2 - 3 u^2)] + E (f_eq - f_rest),
         // p (3 eu + 9 eu^2 - 3 u^2) = theta [(e.j)(1 + 3 e.u) - j.u] with p = rho theta / 3
-        const float E = a.E0 * (1.f + m.dth) + 0.5f * u2;
-        const float K0 = a.rho0 * (a.E0 * m.dth + 0.5f * u2);
-        const float third = 1.f / 3.f;
-        const float Pt = 1.f + th;
-        const float Pd = (drho + rth * (2.f + th)) * third;
-        const float k0 = K0 - Pd - Pt * ju, k1 = K0 + 0.5f * Pd - Pt * ju, k2 = K0 + 2.f * Pd - Pt * ju;
+        const real E = a.E0 * (real(1.) + m.dth) + real(0.5) * u2;
+        const real K0 = a.rho0 * (a.E0 * m.dth + real(0.5) * u2);
+        const real third = real(1.) / real(3.);
+        const real Pt = real(1.) + th;
+        const real Pd = (drho + rth * (real(2.) + th)) * third;
+        const real k0 = K0 - Pd - Pt * ju, k1 = K0 + real(0.5) * Pd - Pt * ju, k2 = K0 + real(2.) * Pd - Pt * ju;
         he[0] = w0 * k0 + E * fe[0];
-        he[1] = w1 * (k1 + Pt * jx * (1.f + 3.f * ux)) + E * fe[1];
-        he[3] = w1 * (k1 - Pt * jx * (1.f - 3.f * ux)) + E * fe[3];
-        he[2] = w1 * (k1 + Pt * jy * (1.f + 3.f * uy)) + E * fe[2];
-        he[4] = w1 * (k1 - Pt * jy * (1.f - 3.f * uy)) + E * fe[4];
-        he[5] = w2 * (k2 + Pt * j5 * (1.f + 3.f * v5)) + E * fe[5];
-        he[7] = w2 * (k2 - Pt * j5 * (1.f - 3.f * v5)) + E * fe[7];
-        he[6] = w2 * (k2 + Pt * j6 * (1.f + 3.f * v6)) + E * fe[6];
-        he[8] = w2 * (k2 - Pt * j6 * (1.f - 3.f * v6)) + E * fe[8];
+        he[1] = w1 * (k1 + Pt * jx * (real(1.) + real(3.) * ux)) + E * fe[1];
+        he[3] = w1 * (k1 - Pt * jx * (real(1.) - real(3.) * ux)) + E * fe[3];
+        he[2] = w1 * (k1 + Pt * jy * (real(1.) + real(3.) * uy)) + E * fe[2];
+        he[4] = w1 * (k1 - Pt * jy * (real(1.) - real(3.) * uy)) + E * fe[4];
+        he[5] = w2 * (k2 + Pt * j5 * (real(1.) + real(3.) * v5)) + E * fe[5];
+        he[7] = w2 * (k2 - Pt * j5 * (real(1.) - real(3.) * v5)) + E * fe[7];
+        he[6] = w2 * (k2 + Pt * j6 * (real(1.) + real(3.) * v6)) + E * fe[6];
+        he[8] = w2 * (k2 - Pt * j6 * (real(1.) - real(3.) * v6)) + E * fe[8];
     } else {
-        const float c = a.rho0 * a.E0 * m.dth, Et = a.E0 * (1.f + m.dth);
+        const real c = a.rho0 * a.E0 * m.dth, Et = a.E0 * (real(1.) + m.dth);
         he[0] = w0 * c + Et * fe[0];
 #pragma unroll
         for (int q = 1; q < 5; ++q) he[q] = w1 * c + Et * fe[q];
@@ -313,14 +339,14 @@ __device__ __forceinline__ void equilibria(const KArgs &a, const Mom &m, float f
 }
 
 struct Relax {
-    float s_nu, s_e, s_z, omega_h, kcoup;
+    real s_nu, s_e, s_z, omega_h, kcoup;
 };
 
 // Per-node transport: tau_f = mu(T) / p + 1/2 (Sec. IV-C) for the viscosity
 // laws, tau_h = (tau_f - 1/2)/Pr, omega_h = 2/(2 tau_h + 1),
 // coupling factor (1 - omega_h/2)(Pr - 1)/tau_f (Eq. 47).
 template <class F>
-__device__ __forceinline__ Relax transport(const KArgs &a, float rho, float dth) {
+__device__ __forceinline__ Relax transport(const KArgs &a, real rho, real dth) {
     Relax t;
     if (F_CTAU) {
         t.s_nu = a.s_nu;
@@ -330,18 +356,18 @@ __device__ __forceinline__ Relax transport(const KArgs &a, float rho, float dth)
         t.kcoup = a.kcoup;
         return t;
     }
-    const float th = 1.f + dth;
-    float mu3 = a.mu3;
+    const real th = real(1.) + dth;
+    real mu3 = a.mu3;
     if (a.visc == LB_VISC_POWER) {
         mu3 *= exp2f(a.visc_n * log2f(a.cT * th));
     } else if (a.visc == LB_VISC_SUTHERLAND) {
-        const float r = a.cT * th;
-        mu3 *= r * sqrtf(r) * (1.f + a.sT) * frcp(r + a.sT);
+        const real r = a.cT * th;
+        mu3 *= r * sqrt(r) * (real(1.) + a.sT) * frcp(r + a.sT);
     }
-    const float tau = mu3 * frcp(rho * th) + 0.5f;  // p = rho R T = rho theta / 3
+    const real tau = mu3 * frcp(rho * th) + real(0.5);  // p = rho R T = rho theta / 3
     t.s_nu = frcp(tau);
-    t.omega_h = 2.f * a.Pr * frcp(2.f * tau - 1.f + a.Pr);
-    t.kcoup = (1.f - 0.5f * t.omega_h) * (a.Pr - 1.f) * t.s_nu;
+    t.omega_h = real(2.) * a.Pr * frcp(real(2.) * tau - real(1.) + a.Pr);
+    t.kcoup = (real(1.) - real(0.5) * t.omega_h) * (a.Pr - real(1.)) * t.s_nu;
     t.s_e = a.tie_e ? t.s_nu : a.s_e;
     t.s_z = a.tie_z ? t.s_nu : a.s_z;
     return t;
@@ -351,7 +377,7 @@ __device__ __forceinline__ Relax transport(const KArgs &a, float rho, float dth)
 // the diagonal at corners), for the node (x, y) of the domain.
 struct BInfo {
     int kind, fx, fy;
-    float ux, uy, dth;
+    real ux, uy, dth;
 };
 
 __device__ __forceinline__ BInfo classify(const KArgs &a, int x, int y) {
@@ -359,7 +385,7 @@ __device__ __forceinline__ BInfo classify(const KArgs &a, int x, int y) {
     b.kind = K_INTERIOR;
     b.fx = x;
     b.fy = y;
-    b.ux = b.uy = b.dth = 0.f;
+    b.ux = b.uy = b.dth = real(0.);
     int hx = -1, hy = -1;
     if (!a.per_x) {
         if (x == 0) hx = 0;
@@ -401,7 +427,7 @@ __device__ __forceinline__ BInfo classify(const KArgs &a, int x, int y) {
 // node itself otherwise), node_finish computes the moments and rebuilds the
 // populations of boundary nodes.  Returns the node kind.
 template <int ST, bool BC>
-__device__ __forceinline__ void node_issue(const KArgs &a, const Planes &S, int x, int y, float d[18]) {
+__device__ __forceinline__ void node_issue(const KArgs &a, const Planes &S, int x, int y, real d[18]) {
     if (!BC) {
         gather<ST>(a, S, x, y, d);
         return;
@@ -411,7 +437,7 @@ __device__ __forceinline__ void node_issue(const KArgs &a, const Planes &S, int 
 }
 
 template <int ST, bool BC, class F>
-__device__ __forceinline__ int node_finish(const KArgs &a, const Planes &S, int x, int y, float d[18], Mom &m) {
+__device__ __forceinline__ int node_finish(const KArgs &a, const Planes &S, int x, int y, real d[18], Mom &m) {
     m = moments<F>(a, d);
     if (!BC) return K_INTERIOR;
     const BInfo b = classify(a, x, y);
@@ -420,12 +446,12 @@ __device__ __forceinline__ int node_finish(const KArgs &a, const Planes &S, int 
     if (b.kind == K_INLET) {
         mb.drho = a.in_drho;
         mb.ux = a.in_ux;
-        mb.uy = 0.f;
+        mb.uy = real(0.);
         mb.dth = a.in_dth;
         mb.rho = a.rho0 + mb.drho;
         mb.jx = mb.rho * mb.ux;
-        mb.jy = 0.f;
-        float he[9];
+        mb.jy = real(0.);
+        real he[9];
         equilibria<F>(a, mb, d, he);
 #pragma unroll
         for (int q = 0; q < 9; ++q) d[9 + q] = he[q];
@@ -442,26 +468,26 @@ __device__ __forceinline__ int node_finish(const KArgs &a, const Planes &S, int 
         mb.dth = b.dth;
     } else {
         // T_b = (4 T_1 - T_2) / 3 along the inward normal
-        float d2[18];
+        real d2[18];
         gather<ST>(a, S, 2 * b.fx - x, 2 * b.fy - y, d2);
         const Mom m2 = moments<F>(a, d2);
-        mb.dth = (4.f * m.dth - m2.dth) * (1.f / 3.f);
+        mb.dth = (real(4.) * m.dth - m2.dth) * (real(1.) / real(3.));
     }
     // pressure extrapolation with the hydrostatic balance of the body force,
     // p_b = p_f exp(x), x = g (y_f - y_b) / (R T_m), T_m = (T_f + T_b)/2
     // (R T0 = 1/3), i.e. rho_b = rho_f theta_f / theta_b (1 + expm1(x));
     // or density extrapolation rho_b = rho_f
     if (a.rho_press) {
-        const float x = 6.f * a.g * (float)(b.fy - y) * frcp(2.f + m.dth + mb.dth);
-        const float em1 = x * (1.f + x * (0.5f + x * (1.f / 6.f + x * (1.f / 24.f))));
-        mb.drho = m.drho + m.rho * ((m.dth - mb.dth) + (1.f + m.dth) * em1) * frcp(1.f + mb.dth);
+        const real x = real(6.) * a.g * (real)(b.fy - y) * frcp(real(2.) + m.dth + mb.dth);
+        const real em1 = x * (real(1.) + x * (real(0.5) + x * (real(1.) / real(6.) + x * (real(1.) / real(24.)))));
+        mb.drho = m.drho + m.rho * ((m.dth - mb.dth) + (real(1.) + m.dth) * em1) * frcp(real(1.) + mb.dth);
     } else {
         mb.drho = m.drho;
     }
     mb.rho = a.rho0 + mb.drho;
     mb.jx = mb.rho * mb.ux;
     mb.jy = mb.rho * mb.uy;
-    float fb[9], hb[9], ff[9], hf[9];
+    real fb[9], hb[9], ff[9], hf[9];
     equilibria<F>(a, mb, fb, hb);
     equilibria<F>(a, m, ff, hf);
 #pragma unroll
@@ -478,7 +504,7 @@ __device__ __forceinline__ int node_finish(const KArgs &a, const Planes &S, int 
 }
 
 template <int ST, bool BC>
-__device__ __forceinline__ int node_state(const KArgs &a, const Planes &S, int x, int y, float d[18], Mom &m) {
+__device__ __forceinline__ int node_state(const KArgs &a, const Planes &S, int x, int y, real d[18], Mom &m) {
     node_issue<ST, BC>(a, S, x, y, d);
     return node_finish<ST, BC, Dyn>(a, S, x, y, d, m);
 }
@@ -486,9 +512,9 @@ __device__ __forceinline__ int node_state(const KArgs &a, const Planes &S, int x
 // Collision of one node (Eq. 44 or Eq. 34 for f^, Eq. 47 or Eq. 38 for h-),
 // deviations in d, results in o.
 template <class F>
-__device__ __forceinline__ void collide(const KArgs &a, const float d[18], const Mom &m, int kind, float phix,
-                                        float phiy, float o[18]) {
-    float fe[9], he[9];
+__device__ __forceinline__ void collide(const KArgs &a, const real d[18], const Mom &m, int kind, real phix,
+                                        real phiy, real o[18]) {
+    real fe[9], he[9];
     equilibria<F>(a, m, fe, he);
     if (kind == K_INLET) {
 #pragma unroll
@@ -499,76 +525,76 @@ __device__ __forceinline__ void collide(const KArgs &a, const float d[18], const
         return;
     }
     const Relax t = transport<F>(a, m.rho, m.dth);
-    const float ux = m.ux, uy = m.uy;
-    const float ay = -m.rho * a.g;
+    const real ux = m.ux, uy = m.uy;
+    const real ay = -m.rho * a.g;
     // velocity-space sources C = M^-1 (C^ + F^): Eq. 49 plus the forcing term
-    const float w0 = 4.f / 9.f, w1 = 1.f / 9.f, w2 = 1.f / 36.f;
-    float C[9];
+    const real w0 = real(4.) / real(9.), w1 = real(1.) / real(9.), w2 = real(1.) / real(36.);
+    real C[9];
     {
-        const float cx0 = -phix * (1.f / 9.f), cx1 = -phix * (1.f / 36.f), cx2 = phix * (1.f / 18.f);
-        const float cy = 0.25f * phiy;
+        const real cx0 = -phix * (real(1.) / real(9.)), cx1 = -phix * (real(1.) / real(36.)), cx2 = phix * (real(1.) / real(18.));
+        const real cy = real(0.25) * phiy;
         C[0] = cx0;
         C[1] = C[3] = cx1 + cy;
         C[2] = C[4] = cx1 - cy;
         C[5] = C[6] = C[7] = C[8] = cx2;
         if (F_FORCE) {
-            const float f3 = -3.f * uy * ay;
+            const real f3 = -real(3.) * uy * ay;
             C[0] += w0 * f3;
             C[1] += w1 * f3;
             C[3] += w1 * f3;
-            C[2] += w1 * ay * (3.f + 6.f * uy);
-            C[4] += w1 * ay * (-3.f + 6.f * uy);
-            C[5] += w2 * ay * (3.f + 9.f * ux + 6.f * uy);
-            C[6] += w2 * ay * (3.f - 9.f * ux + 6.f * uy);
-            C[7] += w2 * ay * (-3.f + 9.f * ux + 6.f * uy);
-            C[8] += w2 * ay * (-3.f - 9.f * ux + 6.f * uy);
+            C[2] += w1 * ay * (real(3.) + real(6.) * uy);
+            C[4] += w1 * ay * (-real(3.) + real(6.) * uy);
+            C[5] += w2 * ay * (real(3.) + real(9.) * ux + real(6.) * uy);
+            C[6] += w2 * ay * (real(3.) - real(9.) * ux + real(6.) * uy);
+            C[7] += w2 * ay * (-real(3.) + real(9.) * ux + real(6.) * uy);
+            C[8] += w2 * ay * (-real(3.) - real(9.) * ux + real(6.) * uy);
         }
     }
     {
         // BGK (Eq. 34) is the MRT scheme with every rate equal to 1/tau_f, so both
         // run through the same moment-space increments.
-        const float sr = F_BGK ? t.s_nu : a.s_rho, sj = F_BGK ? t.s_nu : a.s_j;
-        const float se = F_BGK ? t.s_nu : t.s_e, sz = F_BGK ? t.s_nu : t.s_z, sq = F_BGK ? t.s_nu : a.s_q;
+        const real sr = F_BGK ? t.s_nu : a.s_rho, sj = F_BGK ? t.s_nu : a.s_j;
+        const real se = F_BGK ? t.s_nu : t.s_e, sz = F_BGK ? t.s_nu : t.s_z, sq = F_BGK ? t.s_nu : a.s_q;
         // moments of the deviations, m = M f (Eq. B1); the conserved ones are
         // the raw sums, so that their increments vanish exactly on interior nodes
-        const float s1 = (d[1] + d[3]) + (d[2] + d[4]);
-        const float s2 = (d[5] + d[7]) + (d[6] + d[8]);
-        const float dx13 = d[1] - d[3], dy24 = d[2] - d[4];
-        const float a57 = d[5] - d[7], a86 = d[8] - d[6], a68 = d[6] - d[8];
-        const float m1 = -4.f * d[0] - s1 + 2.f * s2;
-        const float m2 = 4.f * d[0] - 2.f * s1 + s2;
-        const float m4 = -2.f * dx13 + (a57 + a86);
-        const float m6 = -2.f * dy24 + (a57 + a68);
-        const float m7 = (d[1] + d[3]) - (d[2] + d[4]);
-        const float m8 = (d[5] + d[7]) - (d[6] + d[8]);
+        const real s1 = (d[1] + d[3]) + (d[2] + d[4]);
+        const real s2 = (d[5] + d[7]) + (d[6] + d[8]);
+        const real dx13 = d[1] - d[3], dy24 = d[2] - d[4];
+        const real a57 = d[5] - d[7], a86 = d[8] - d[6], a68 = d[6] - d[8];
+        const real m1 = -real(4.) * d[0] - s1 + real(2.) * s2;
+        const real m2 = real(4.) * d[0] - real(2.) * s1 + s2;
+        const real m4 = -real(2.) * dx13 + (a57 + a86);
+        const real m6 = -real(2.) * dy24 + (a57 + a68);
+        const real m7 = (d[1] + d[3]) - (d[2] + d[4]);
+        const real m8 = (d[5] + d[7]) - (d[6] + d[8]);
         // equilibria Eq. 41 minus M f_rest
-        const float thE = F_COUPLED ? m.dth : 0.f;
-        const float rho = m.rho;
-        const float qq = 3.f * (m.jx * ux + m.jy * uy) + 2.f * rho * thE;
-        const float e1 = -2.f * m.drho + qq, e2 = m.drho - qq;
-        const float e4 = -m.jx * (1.f - thE), e6 = -m.jy * (1.f - thE);
-        const float e7 = m.jx * ux - m.jy * uy, e8 = m.jx * uy;
+        const real thE = F_COUPLED ? m.dth : real(0.);
+        const real rho = m.rho;
+        const real qq = real(3.) * (m.jx * ux + m.jy * uy) + real(2.) * rho * thE;
+        const real e1 = -real(2.) * m.drho + qq, e2 = m.drho - qq;
+        const real e4 = -m.jx * (real(1.) - thE), e6 = -m.jy * (real(1.) - thE);
+        const real e7 = m.jx * ux - m.jy * uy, e8 = m.jx * uy;
         // sources C^ = (0, phi_x, 0, 0, 0, 0, 0, phi_y, 0) + F^ (Eq. 48, 51)
-        const float uay = uy * ay;
-        const float c1 = phix + 6.f * uay, c2 = -6.f * uay, c5 = ay, c6 = -ay, c7 = phiy - 2.f * uay, c8 = ux * ay;
+        const real uay = uy * ay;
+        const real c1 = phix + real(6.) * uay, c2 = -real(6.) * uay, c5 = ay, c6 = -ay, c7 = phiy - real(2.) * uay, c8 = ux * ay;
         // Eq. 44 as increments dm = m* - m
-        const float g0 = -sr * (m.sf - m.drho);
-        const float g1 = -se * (m1 - e1) + (1.f - 0.5f * se) * c1;
-        const float g2 = -sz * (m2 - e2) + (1.f - 0.5f * sz) * c2;
-        const float g3 = -sj * (m.sx - m.jx);
-        const float g4 = -sq * (m4 - e4);
-        const float g5 = -sj * (m.sy - m.jy) + (1.f - 0.5f * sj) * c5;
-        const float g6 = -sq * (m6 - e6) + (1.f - 0.5f * sq) * c6;
-        const float g7 = -t.s_nu * (m7 - e7) + (1.f - 0.5f * t.s_nu) * c7;
-        const float g8 = -t.s_nu * (m8 - e8) + (1.f - 0.5f * t.s_nu) * c8;
+        const real g0 = -sr * (m.sf - m.drho);
+        const real g1 = -se * (m1 - e1) + (real(1.) - real(0.5) * se) * c1;
+        const real g2 = -sz * (m2 - e2) + (real(1.) - real(0.5) * sz) * c2;
+        const real g3 = -sj * (m.sx - m.jx);
+        const real g4 = -sq * (m4 - e4);
+        const real g5 = -sj * (m.sy - m.jy) + (real(1.) - real(0.5) * sj) * c5;
+        const real g6 = -sq * (m6 - e6) + (real(1.) - real(0.5) * sq) * c6;
+        const real g7 = -t.s_nu * (m7 - e7) + (real(1.) - real(0.5) * t.s_nu) * c7;
+        const real g8 = -t.s_nu * (m8 - e8) + (real(1.) - real(0.5) * t.s_nu) * c8;
         // f* = f + M^-1 dm (Eq. B2)
-        const float A = g0 * (1.f / 9.f);
-        const float a1 = A - g1 * (1.f / 36.f) - g2 * (1.f / 18.f);
-        const float a2 = A + g1 * (1.f / 18.f) + g2 * (1.f / 36.f);
-        const float X = (g3 - g4) * (1.f / 6.f), Y = (g5 - g6) * (1.f / 6.f), P = 0.25f * g7;
-        const float X2 = g3 * (1.f / 6.f) + g4 * (1.f / 12.f), Y2 = g5 * (1.f / 6.f) + g6 * (1.f / 12.f);
-        const float Pxy = 0.25f * g8;
-        o[0] = d[0] + (A + (g2 - g1) * (1.f / 9.f));
+        const real A = g0 * (real(1.) / real(9.));
+        const real a1 = A - g1 * (real(1.) / real(36.)) - g2 * (real(1.) / real(18.));
+        const real a2 = A + g1 * (real(1.) / real(18.)) + g2 * (real(1.) / real(36.));
+        const real X = (g3 - g4) * (real(1.) / real(6.)), Y = (g5 - g6) * (real(1.) / real(6.)), P = real(0.25) * g7;
+        const real X2 = g3 * (real(1.) / real(6.)) + g4 * (real(1.) / real(12.)), Y2 = g5 * (real(1.) / real(6.)) + g6 * (real(1.) / real(12.));
+        const real Pxy = real(0.25) * g8;
+        o[0] = d[0] + (A + (g2 - g1) * (real(1.) / real(9.)));
         o[1] = d[1] + (a1 + X + P);
         o[3] = d[3] + (a1 - X + P);
         o[2] = d[2] + (a1 + Y - P);
@@ -579,15 +605,15 @@ __device__ __forceinline__ void collide(const KArgs &a, const float d[18], const
         o[8] = d[8] + (a2 + X2 - Y2 - Pxy);
     }
     // h: BGK plus the coupling term (1 - omega_h/2)(Z/tau_hf)(f - f_eq + C/2), Z = e.u
-    const float wh = t.omega_h;
+    const real wh = t.omega_h;
 #pragma unroll
     for (int q = 0; q < 9; ++q) o[9 + q] = d[9 + q] - wh * (d[9 + q] - he[q]);
     if (F_HEAT) {
-        const float k = t.kcoup;
-        const float v5 = ux + uy, v6 = uy - ux;
-        const float z[9] = {0.f, ux, uy, -ux, -uy, v5, v6, -v5, -v6};
+        const real k = t.kcoup;
+        const real v5 = ux + uy, v6 = uy - ux;
+        const real z[9] = {real(0.), ux, uy, -ux, -uy, v5, v6, -v5, -v6};
 #pragma unroll
-        for (int q = 1; q < 9; ++q) o[9 + q] += k * z[q] * (d[q] - fe[q] + 0.5f * C[q]);
+        for (int q = 1; q < 9; ++q) o[9 + q] += k * z[q] * (d[q] - fe[q] + real(0.5) * C[q]);
     }
 }
 
@@ -625,7 +651,7 @@ __device__ __forceinline__ int row_wrap(const KArgs &a, int y, bool &yin) {
 }
 
 template <int ST, bool BC>
-__device__ __forceinline__ void row_issue(const KArgs &a, const Planes &S, int xw, int y, float d[18]) {
+__device__ __forceinline__ void row_issue(const KArgs &a, const Planes &S, int xw, int y, real d[18]) {
     bool yin;
     const int yw = row_wrap(a, y, yin);
     node_issue<ST, BC>(a, S, xw, yw, d);
@@ -633,12 +659,12 @@ __device__ __forceinline__ void row_issue(const KArgs &a, const Planes &S, int x
 
 // Moments, kind and Q = rho u (1 - theta) (Eq. 48) of the lane's node in row y.
 template <int ST, bool BC, class F>
-__device__ __forceinline__ int row_finish(const KArgs &a, const Planes &S, int xw, bool xin, int y, float d[18],
-                                          Mom &m, float &Qx, float &Qy) {
+__device__ __forceinline__ int row_finish(const KArgs &a, const Planes &S, int xw, bool xin, int y, real d[18],
+                                          Mom &m, real &Qx, real &Qy) {
     bool yin;
     const int yw = row_wrap(a, y, yin);
     const int kind = node_finish<ST, BC, F>(a, S, xw, yw, d, m);
-    const float mq = (F_CORR && xin && yin) ? -m.rho * m.dth : 0.f;
+    const real mq = (F_CORR && xin && yin) ? -m.rho * m.dth : real(0.);
     Qx = mq * m.ux;
     Qy = mq * m.uy;
     return kind;
@@ -648,16 +674,16 @@ __device__ __forceinline__ int row_finish(const KArgs &a, const Planes &S, int x
 // x-neighbours from the adjacent lanes, the two tile-edge neighbours from the
 // halo values qhl, qhr), collision, store of the owned lanes.
 template <int ST, bool BC, class F>
-__device__ __forceinline__ void collide_store(const KArgs &a, const Planes &D, const float d[18], const Mom &m,
-                                              int kind, int lane, float qxc, float qhl, float qhr, float qyp,
-                                              float qyn, bool owned, unsigned vo, unsigned step) {
-    float qxl = __shfl_up(qxc, 1), qxr = __shfl_down(qxc, 1);
+__device__ __forceinline__ void collide_store(const KArgs &a, const Planes &D, const real d[18], const Mom &m,
+                                              int kind, int lane, real qxc, real qhl, real qhr, real qyp,
+                                              real qyn, bool owned, unsigned vo, unsigned step) {
+    real qxl = __shfl_up(qxc, 1), qxr = __shfl_down(qxc, 1);
     qxl = lane == 0 ? qhl : qxl;
     qxr = lane == kWave - 1 ? qhr : qxr;
-    const float dQx = 0.5f * (qxr - qxl), dQy = 0.5f * (qyn - qyp);
-    float phix = 3.f * (dQx + dQy), phiy = dQx - dQy;
-    if (BC && kind != K_INTERIOR) phix = phiy = 0.f;
-    float o[18];
+    const real dQx = real(0.5) * (qxr - qxl), dQy = real(0.5) * (qyn - qyp);
+    real phix = real(3.) * (dQx + dQy), phiy = dQx - dQy;
+    if (BC && kind != K_INTERIOR) phix = phiy = real(0.);
+    real o[18];
     collide<F>(a, d, m, kind, phix, phiy, o);
     if (owned) {
         const unsigned h = ST == LB_STORE_F32 ? 0u : hash32((vo / Codec<ST>::bytes) ^ (step * 0x9E3779B9u));
@@ -685,17 +711,17 @@ __device__ __forceinline__ int col_wrap(const KArgs &a, int x, bool &xin) {
 // unused, and a side that is not needed is skipped.  One wide gather thus
 // serves 32 rows; the row loop picks its values out with readlane.
 template <int ST, bool BC, class F>
-__device__ __forceinline__ float halo_chunk(const KArgs &a, const Planes &S, int x0, int lane, int yb, int dir,
+__device__ __forceinline__ real halo_chunk(const KArgs &a, const Planes &S, int x0, int lane, int yb, int dir,
                                             int ylo, int yhi, bool need_l, bool need_r) {
     const bool left = lane < kHaloRows;
-    float qx = 0.f;
+    real qx = real(0.);
     if (left ? need_l : need_r) {
         bool hxin;
         const int hxw = col_wrap(a, left ? x0 - 1 : x0 + kTile, hxin);
         const int hy = min(max(yb + dir * (lane & (kHaloRows - 1)), ylo), yhi);
-        float dh[18];
+        real dh[18];
         Mom mh;
-        float qy;
+        real qy;
         row_issue<ST, BC>(a, S, hxw, hy, dh);
         row_finish<ST, BC, F>(a, S, hxw, hxin, hy, dh, mh, qx, qy);
     }
@@ -718,7 +744,7 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
                                           int tx, int sy, unsigned step) {
     // Q_x of the edge lanes (0: lane 0, 1: lane 63) of each wavefront, three
     // row slots so that one barrier per row separates writes from reads
-    __shared__ float qedge[3][LW][2];
+    __shared__ real qedge[3][LW][2];
     const int lane = threadIdx.x & (kWave - 1);
     const int w = LW > 1 ? (int)(threadIdx.x >> 6) : 0;
     const bool edge_l = w == 0, edge_r = w == LW - 1;
@@ -737,14 +763,14 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
     unsigned vo = ((unsigned)ys * a.rs + xw) * eb;
 
     // halo Q_x from the gathered chunk (outer wavefronts only)
-    float qh = 0.f;
+    real qh = real(0.);
     if (edge_l || edge_r) qh = halo_chunk<ST, BC, F>(a, S, x0, lane, ys, dir, y0, y1 - 1, edge_l, edge_r);
 
     // two row states used alternately (the loop is unrolled by two); qyb is
     // Q_y of the row behind the current one
-    float dA[18], dB[18];
+    real dA[18], dB[18];
     Mom mA, mB;
-    float qyb, qxA, qyA, qxB, qyB;
+    real qyb, qxA, qyA, qxB, qyB;
     row_issue<ST, BC>(a, S, xw, ys - dir, dA);
     row_finish<ST, BC, F>(a, S, xw, xin, ys - dir, dA, mA, qxA, qyb);
     row_issue<ST, BC>(a, S, xw, ys, dA);
@@ -757,15 +783,15 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
 
     // One row (k rows into the march): issue the look-ahead row's loads,
     // finish it, publish its edge Q_x, then collide and store the current row.
-    auto row = [&](int k, float(&dC)[18], const Mom &mC, int kC, float qxC, float(&dN)[18], Mom &mN, int &kN,
-                   float &qxN, float &qyN) {
+    auto row = [&](int k, real(&dC)[18], const Mom &mC, int kC, real qxC, real(&dN)[18], Mom &mN, int &kN,
+                   real &qxN, real &qyN) {
         const int y = ys + dir * k;
         row_issue<ST, BC>(a, S, xw, y + dir, dN);
         const int r = k & (kHaloRows - 1);
         if ((edge_l || edge_r) && r == 0 && k != 0)
             qh = halo_chunk<ST, BC, F>(a, S, x0, lane, y, dir, y0, y1 - 1, edge_l, edge_r);
-        float qhl = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qh), r));
-        float qhr = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qh), kHaloRows + r));
+        real qhl = readlane_real(qh, r);
+        real qhr = readlane_real(qh, kHaloRows + r);
         kN = row_finish<ST, BC, F>(a, S, xw, xin, y + dir, dN, mN, qxN, qyN);
         if (LW > 1) {
             const int sn = sc == 2 ? 0 : sc + 1;
@@ -777,7 +803,7 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
             sc = sn;
         }
         // Q_y at y - 1 and y + 1
-        const float qym = dir > 0 ? qyb : qyN, qyq = dir > 0 ? qyN : qyb;
+        const real qym = dir > 0 ? qyb : qyN, qyq = dir > 0 ? qyN : qyb;
         collide_store<ST, BC, F>(a, D, dC, mC, kC, lane, qxC, qhl, qhr, qym, qyq, owned, vo, step);
         vo += dvo;
     };
@@ -888,8 +914,8 @@ __global__ __launch_bounds__(kBlock) void k_init(const KArgs a, const float *__r
     m.rho = a.rho0 + m.drho;
     m.jx = m.rho * m.ux;
     m.jy = m.rho * m.uy;
-    m.sf = m.sx = m.sy = 0.f;
-    float fe[9], he[9];
+    m.sf = m.sx = m.sy = real(0.);
+    real fe[9], he[9];
     equilibria<Dyn>(a, m, fe, he);
     const Planes D = planes(dst, a);
     const int ex[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
@@ -916,18 +942,18 @@ __global__ __launch_bounds__(kBlock) void k_init(const KArgs a, const float *__r
 template <int ST, bool BC>
 __global__ __launch_bounds__(kBlock) void k_macros(const KArgs a, const char *__restrict__ src, float *__restrict__ o0,
                                                    float *__restrict__ o1, float *__restrict__ o2,
-                                                   float *__restrict__ o3, int opitch, int full, float tscale) {
+                                                   float *__restrict__ o3, int opitch, int full, real tscale) {
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.nx * a.ny) return;
     const int x = i % a.nx, y = i / a.nx;
-    float d[18];
+    real d[18];
     Mom m;
     node_state<ST, BC>(a, planes(src, a), x, y, d, m);
     const unsigned k = (unsigned)y * opitch + x;
     if (o0) o0[k] = full ? m.rho : m.drho;
     if (o1) o1[k] = m.ux;
     if (o2) o2[k] = m.uy;
-    if (o3) o3[k] = full ? tscale * (1.f + m.dth) : m.dth;
+    if (o3) o3[k] = full ? tscale * (real(1.) + m.dth) : m.dth;
 }
 
 // Population deviations after the boundary treatment, planes q0 .. q0+nq-1.
@@ -937,7 +963,7 @@ __global__ __launch_bounds__(kBlock) void k_pops(const KArgs a, const char *__re
     const int i = blockIdx.x * kBlock + threadIdx.x;
     if (i >= a.nx * a.ny) return;
     const int x = i % a.nx, y = i / a.nx;
-    float d[18];
+    real d[18];
     Mom m;
     node_state<ST, BC>(a, planes(src, a), x, y, d, m);
     const unsigned k = (unsigned)y * a.pitch + x;
@@ -962,7 +988,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(const KArgs a, const char *__re
     const Planes P = planes(src, a);
     for (int i = blockIdx.x * kBlock + threadIdx.x; i < n; i += gridDim.x * kBlock) {
         const int x = i % a.nx, y = i / a.nx;
-        float d[18];
+        real d[18];
         Mom m;
         node_state<ST, BC>(a, P, x, y, d, m);
         double sf = 0, sh = 0;
@@ -975,8 +1001,8 @@ __global__ __launch_bounds__(kBlock) void k_diag(const KArgs a, const char *__re
         acc[1] += sh;
         acc[2] += ((double)d[1] - d[3]) + ((double)d[5] - d[6]) + ((double)d[8] - d[7]);
         acc[3] += ((double)d[2] - d[4]) + ((double)d[5] + d[6]) - ((double)d[7] + d[8]);
-        const bool ok = isfinite(m.rho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(m.dth) && m.rho > 0.f &&
-                        (1.f + m.dth) > 0.f;
+        const bool ok = isfinite(m.rho) && isfinite(m.ux) && isfinite(m.uy) && isfinite(m.dth) && m.rho > real(0.) &&
+                        (real(1.) + m.dth) > real(0.);
         acc[4] += ok ? 0.0 : 1.0;
         const unsigned k = (unsigned)y * a.pitch + x;
         if (use_snap) {
@@ -1187,39 +1213,39 @@ KArgs make_args(const lb_params *p, const Layout &L, double &E0out) {
     a.has_force = p->g != 0.0;
     const double E0 = 0.5 * p->b * p->R * p->T0;
     E0out = E0;
-    a.rho0 = (float)p->rho0;
-    a.E0 = (float)E0;
-    a.inv_E0 = (float)(1.0 / E0);
-    a.g = (float)p->g;
-    a.half_g = (float)(0.5 * p->g);
-    a.Pr = (float)p->Pr;
+    a.rho0 = (real)p->rho0;
+    a.E0 = (real)E0;
+    a.inv_E0 = (real)(1.0 / E0);
+    a.g = (real)p->g;
+    a.half_g = (real)(0.5 * p->g);
+    a.Pr = (real)p->Pr;
     if (p->visc == LB_VISC_CONST_TAU) {
         const double tau = p->tau_f, snu = 1.0 / tau;
         const double tau_h = (tau - 0.5) / p->Pr;
         const double wh = 2.0 / (2.0 * tau_h + 1.0);
-        a.s_nu = (float)snu;
-        a.omega_h = (float)wh;
-        a.kcoup = (float)((1.0 - 0.5 * wh) * (p->Pr - 1.0) / tau);
-        a.s_e = (float)(p->s_e > 0 ? p->s_e : snu);
-        a.s_z = (float)(p->s_zeta > 0 ? p->s_zeta : snu);
+        a.s_nu = (real)snu;
+        a.omega_h = (real)wh;
+        a.kcoup = (real)((1.0 - 0.5 * wh) * (p->Pr - 1.0) / tau);
+        a.s_e = (real)(p->s_e > 0 ? p->s_e : snu);
+        a.s_z = (real)(p->s_zeta > 0 ? p->s_zeta : snu);
     } else {
-        a.s_e = (float)p->s_e;
-        a.s_z = (float)p->s_zeta;
+        a.s_e = (real)p->s_e;
+        a.s_z = (real)p->s_zeta;
     }
     a.tie_e = !(p->s_e > 0);
     a.tie_z = !(p->s_zeta > 0);
-    a.s_q = (float)p->s_q;
-    a.s_rho = (float)(1.0 / p->tau_rho);
-    a.s_j = (float)(1.0 / p->tau_j);
-    a.mu3 = (float)(3.0 * p->mu_ref);
-    a.cT = (float)(p->T0 / p->T_ref);
-    a.visc_n = (float)p->visc_n;
-    a.sT = (float)(p->suth_S / p->T_ref);
+    a.s_q = (real)p->s_q;
+    a.s_rho = (real)(1.0 / p->tau_rho);
+    a.s_j = (real)(1.0 / p->tau_j);
+    a.mu3 = (real)(3.0 * p->mu_ref);
+    a.cT = (real)(p->T0 / p->T_ref);
+    a.visc_n = (real)p->visc_n;
+    a.sT = (real)(p->suth_S / p->T_ref);
     for (int s = 0; s < 4; ++s) {
         a.side_kind[s] = p->side[s].kind;
-        a.side_ux[s] = (float)p->side[s].ux;
-        a.side_uy[s] = (float)p->side[s].uy;
-        a.side_dth[s] = (float)(p->side[s].T / p->T0 - 1.0);
+        a.side_ux[s] = (real)p->side[s].ux;
+        a.side_uy[s] = (real)p->side[s].uy;
+        a.side_dth[s] = (real)(p->side[s].T / p->T0 - 1.0);
     }
     return a;
 }
@@ -1234,9 +1260,9 @@ void set_inlet(lb_handle *h, long n) {
     const double ph = std::fmod((double)n, P) / P;
     const double s = std::sin(2.0 * M_PI * ph);
     const double U0 = p.side[0].amp;
-    h->a.in_ux = (float)(U0 * s);
-    h->a.in_drho = (float)(p.rho0 * U0 * s / cs);
-    h->a.in_dth = (float)((gamma - 1.0) * U0 * s / cs);
+    h->a.in_ux = (real)(U0 * s);
+    h->a.in_drho = (real)(p.rho0 * U0 * s / cs);
+    h->a.in_dth = (real)((gamma - 1.0) * U0 * s / cs);
 }
 
 template <int ST, bool BC, class F>

@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbddf.so")
+LIB_PATH = os.path.join(HERE, "liblbddf.so")  # FP32 arithmetic
+# the same ABI with the step's arithmetic in FP64 (storage formats unchanged)
+LIB_PATH_FP64 = os.path.join(HERE, "liblbddf_fp64.so")
 
 LB_OK, LB_EINVAL, LB_ENOMEM, LB_EHIP, LB_EUNSTABLE, LB_EBUSY = 0, -1, -2, -3, -4, -5
 _STORAGE = {"f32": 0, "f16": 1, "bf16": 2}
@@ -50,8 +52,6 @@ class lb_params(C.Structure):
 
 _D = C.POINTER(C.c_double)
 _F = C.POINTER(C.c_float)
-_lib = None
-
 # symbol -> (restype, argtypes)
 _SIGS = {
     "lb_validate": (C.c_int, [C.POINTER(lb_params)]),
@@ -88,29 +88,40 @@ _SIGS = {
 LBS_STATES = {0: "queued", 1: "running", 2: "converged", 3: "plateau", 4: "step_cap", 5: "unstable"}
 
 
-def load():
-    """Loads the in-tree library; raises if it has not been built."""
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
-            raise ImportError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+_libs = {}
+
+
+def load(arith: str = "f32"):
+    """Loads the in-tree library for the arithmetic ("f32", or "f64":
+    liblbddf_fp64.so); raises if it has not been built."""
+    path = {"f32": LIB_PATH, "f64": LIB_PATH_FP64}[arith]
+    lib = _libs.get(path)
+    if lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with __graft_entry__.build()")
         # torch ships its own HIP runtime under the same soname as the system
         # one.  Importing torch first makes the library bind to that runtime,
         # so device pointers and streams from torch are valid in both; loaded
         # the other way round the process would hold two runtimes.
         import torch  # noqa: F401
-        lib = C.CDLL(LIB_PATH)
+        lib = C.CDLL(path)
         for name, (res, args) in _SIGS.items():
             fn = getattr(lib, name)
             fn.restype = res
             fn.argtypes = args
-        _lib = lib
-    return _lib
+        _libs[path] = lib
+    return lib
 
 
-def _check(status):
+def _check_in(lib, status):
+    _check(status, lib)
+
+
+def _check(status, lib=None):
+    """Raises on a failed call; the message comes from the library that
+    failed (each keeps its own last error)."""
     if status != LB_OK:
-        raise LBError(status, load().lb_last_error().decode())
+        raise LBError(status, (lib or load()).lb_last_error().decode())
 
 
 def make_params(p: dict) -> lb_params:
@@ -151,12 +162,14 @@ def _dptr(a):
 
 
 class Solver:
-    """One grid on one GPU: device state in a torch buffer, kernels in liblbddf."""
+    """One grid on one GPU: device state in a torch buffer, kernels in liblbddf
+    (arith="f64": liblbddf_fp64.so, the step's arithmetic in FP64)."""
 
-    def __init__(self, params: dict, device: int = 0, stream=None):
+    def __init__(self, params: dict, device: int = 0, stream=None, arith: str = "f32"):
         import torch
 
-        self.lib = load()
+        self.lib = load(arith)
+        self.arith = arith
         self.p = dict(params)
         self.nx, self.ny = int(params["nx"]), int(params["ny"])
         self._s = make_params(self.p)
@@ -169,7 +182,7 @@ class Solver:
             self.buf = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
-            _check(self.lib.lb_create(C.byref(self._s), C.c_void_p(self.buf.data_ptr()), C.c_size_t(nbytes),
+            _check_in(self.lib, self.lib.lb_create(C.byref(self._s), C.c_void_p(self.buf.data_ptr()), C.c_size_t(nbytes),
                                       C.c_void_p(self.stream.cuda_stream), C.byref(h)))
         self.h = h
 
@@ -193,11 +206,11 @@ class Solver:
 
     def init(self, rho=None, ux=None, uy=None, T=None):
         arrs = [self._field(a) for a in (rho, ux, uy, T)]
-        _check(self.lib.lb_init(self.h, *[_dptr(a) for a in arrs]))
+        _check_in(self.lib, self.lib.lb_init(self.h, *[_dptr(a) for a in arrs]))
         return self
 
     def step(self, n: int = 1):
-        _check(self.lib.lb_step(self.h, int(n)))
+        _check_in(self.lib, self.lib.lb_step(self.h, int(n)))
         return self
 
     @property
@@ -206,47 +219,47 @@ class Solver:
 
     def macros(self):
         out = [np.empty((self.ny, self.nx)) for _ in range(4)]
-        _check(self.lib.lb_macros(self.h, *[_dptr(a) for a in out]))
+        _check_in(self.lib, self.lib.lb_macros(self.h, *[_dptr(a) for a in out]))
         return tuple(out)
 
     def macros_device(self):
         import torch
 
         out = [torch.empty((self.ny, self.nx), dtype=torch.float32, device=self.device) for _ in range(4)]
-        _check(self.lib.lb_macros_device(self.h, *[C.c_void_p(t.data_ptr()) for t in out]))
+        _check_in(self.lib, self.lib.lb_macros_device(self.h, *[C.c_void_p(t.data_ptr()) for t in out]))
         return tuple(out)
 
     def populations(self) -> np.ndarray:
         out = np.empty((18, self.ny, self.nx))
-        _check(self.lib.lb_populations(self.h, _dptr(out)))
+        _check_in(self.lib, self.lib.lb_populations(self.h, _dptr(out)))
         return out
 
     def diag(self, check: bool = True) -> dict:
         out = np.zeros(6)
         st = self.lib.lb_diag(self.h, _dptr(out))
         if check and st != LB_OK:
-            _check(st)
+            _check(st, self.lib)
         return dict(mass=out[0], energy=out[1], jx=out[2], jy=out[3], bad=int(out[4]), time=int(out[5]),
                     status=int(st))
 
     def residual(self, update: bool = True) -> float:
         r = np.zeros(1)
-        _check(self.lib.lb_residual(self.h, int(update), _dptr(r)))
+        _check_in(self.lib, self.lib.lb_residual(self.h, int(update), _dptr(r)))
         return float(r[0])
 
     def save(self) -> bytes:
         n = self.lib.lb_checkpoint_bytes(self.h)
         buf = C.create_string_buffer(int(n))
-        _check(self.lib.lb_save(self.h, buf))
+        _check_in(self.lib, self.lib.lb_save(self.h, buf))
         return buf.raw
 
     def load(self, blob: bytes):
         buf = C.create_string_buffer(blob, len(blob))
-        _check(self.lib.lb_load(self.h, buf))
+        _check_in(self.lib, self.lib.lb_load(self.h, buf))
         return self
 
     def set_strip_rows(self, rows: int):
-        _check(self.lib.lb_set_strip_rows(self.h, int(rows)))
+        _check_in(self.lib, self.lib.lb_set_strip_rows(self.h, int(rows)))
 
     @property
     def strip_rows(self) -> int:
@@ -256,17 +269,18 @@ class Solver:
 class Server:
     """Continuous-batching server over one device pool (the lbs_* calls)."""
 
-    def __init__(self, pool_bytes: int, storage: str = "f32", k_steps: int = 100, device: int = 0, stream=None):
+    def __init__(self, pool_bytes: int, storage: str = "f32", k_steps: int = 100, device: int = 0, stream=None,
+                 arith: str = "f32"):
         import torch
 
-        self.lib = load()
+        self.lib = load(arith)
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         with torch.cuda.device(self.device):
             self.pool = torch.empty(int(pool_bytes), dtype=torch.uint8, device=self.device)
         h = C.c_void_p()
         with torch.cuda.device(self.device):
-            _check(self.lib.lbs_create(C.c_void_p(self.pool.data_ptr()), C.c_size_t(int(pool_bytes)),
+            _check_in(self.lib, self.lib.lbs_create(C.c_void_p(self.pool.data_ptr()), C.c_size_t(int(pool_bytes)),
                                        _STORAGE[storage], int(k_steps), C.c_void_p(self.stream.cuda_stream),
                                        C.byref(h)))
         self.h = h
@@ -294,34 +308,34 @@ class Server:
         for a in arrs:
             assert a is None or a.size == n
         rid = C.c_long()
-        _check(self.lib.lbs_submit(self.h, C.byref(s), *[_dptr(a) for a in arrs], float(tol), int(max_steps),
+        _check_in(self.lib, self.lib.lbs_submit(self.h, C.byref(s), *[_dptr(a) for a in arrs], float(tol), int(max_steps),
                                    C.byref(rid)))
         self.shapes[rid.value] = (int(p["ny"]), int(p["nx"]))
         return rid.value
 
     def advance(self):
         r, q = C.c_int(), C.c_int()
-        _check(self.lib.lbs_advance(self.h, C.byref(r), C.byref(q)))
+        _check_in(self.lib, self.lib.lbs_advance(self.h, C.byref(r), C.byref(q)))
         return r.value, q.value
 
     def poll(self, rid: int) -> dict:
         st, steps, res, t = C.c_int(), C.c_long(), np.zeros(1), np.zeros(3)
-        _check(self.lib.lbs_poll(self.h, int(rid), C.byref(st), C.byref(steps), _dptr(res), _dptr(t)))
+        _check_in(self.lib, self.lib.lbs_poll(self.h, int(rid), C.byref(st), C.byref(steps), _dptr(res), _dptr(t)))
         return dict(state=LBS_STATES[st.value], steps=steps.value, residual=float(res[0]), t_submit=t[0],
                     t_admit=t[1], t_done=t[2])
 
     def result(self, rid: int):
         ny, nx = self.shapes[rid]
         out = [np.empty((ny, nx)) for _ in range(4)]
-        _check(self.lib.lbs_result(self.h, int(rid), *[_dptr(a) for a in out]))
+        _check_in(self.lib, self.lib.lbs_result(self.h, int(rid), *[_dptr(a) for a in out]))
         return tuple(out)
 
     def release(self, rid: int):
-        _check(self.lib.lbs_release(self.h, int(rid)))
+        _check_in(self.lib, self.lib.lbs_release(self.h, int(rid)))
         self.shapes.pop(rid, None)
 
     def stats(self) -> dict:
         o = np.zeros(6)
-        _check(self.lib.lbs_stats(self.h, _dptr(o)))
+        _check_in(self.lib, self.lib.lbs_stats(self.h, _dptr(o)))
         return dict(batches=int(o[0]), node_updates=o[1], busy_s=o[2], finished=int(o[3]), free_bytes=int(o[4]),
                     queued=int(o[5]))

@@ -133,14 +133,21 @@ def test_small_dT_cavity_converged_state_against_the_oracle():
     to 1e-3; the velocity does not meet 1e-5: the flow's velocity (about
     3.5e-3) is driven by a buoyancy 50 times smaller than the hydrostatic
     forces (dT/T0 = 0.02), and FP32 rounding accumulates over the viscous
-    time H^2/nu of some 8e5 steps (measured: 5e-4)."""
+    time H^2/nu of some 8e5 steps (measured: 5e-4).  The same run with the
+    step's arithmetic in FP64 (liblbddf_fp64.so, FP32 storage) meets 1e-5 in
+    all three (measured 1e-8 / 5e-7 / 1e-8)."""
     from oracle import oracle as O
 
     p = W.cavity(128, 1e4, 0.02, 0.02)
     f = W.noisy_temperature_fields(p)
-    print("[case] Table II Ra=1e4 cavity 128x128, 268000 steps, GPU and oracle", flush=True)
+    print("[case] Table II Ra=1e4 cavity 128x128, 268000 steps, GPU (FP32 and FP64 arithmetic) and oracle",
+          flush=True)
     g = lbddf.Solver(p).init(*f).step(268_000).macros()
+    g64 = lbddf.Solver(p, arith="f64").init(*f).step(268_000).macros()
     r = O.Oracle(p).init(*f).step(268_000).macros()
+    e64 = rel_errors(g64, r)
+    print(f"       FP64 arithmetic: rel err rho {e64[0]:.3e} u {e64[1]:.3e} T {e64[2]:.3e}", flush=True)
+    assert max(e64) < TOL["f32"], e64
     e = rel_errors(g, r)
     mg, mr = P.cavity_metrics(p, *g[1:]), P.cavity_metrics(p, *r[1:])
     print(f"       rel err rho {e[0]:.3e} u {e[1]:.3e} T {e[2]:.3e}; Nu {mg['Nu']:.5f} / {mr['Nu']:.5f}, "
@@ -236,7 +243,19 @@ def test_large_dT_cavity_downscale_against_the_oracle(large_dT_reference, storag
         pytest.xfail(f"{storage} storage misses 2e-3 on O(1) deviations from rest: errors {e}")
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+def test_large_dT_cavity_downscale_fp64_arithmetic(large_dT_reference):
+    """The 64 x 64 large-dT form with the step's arithmetic in FP64
+    (liblbddf_fp64.so) and FP32 storage: within 1e-5 of the oracle after
+    200,000 steps (FP32 arithmetic: 3.4e-5)."""
+    p, f, ref = large_dT_reference
+    s = lbddf.Solver(p, arith="f64").init(*f).step(200_000)
+    e = rel_errors(s.macros(), ref)
+    print(f"[case] large-dT cavity 64x64, FP64 arithmetic, 200000 steps: rel err rho {e[0]:.3e} u {e[1]:.3e} "
+          f"T {e[2]:.3e}", flush=True)
+    assert max(e) < TOL["f32"], e
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "bf16", "f32-fp64-arith"])
 def test_large_dT_cavity_512_against_the_oracle(storage):
     """Config 3 at full size: 512 x 512, 200,000 steps, against the FP64
     oracle's fields on every 8th node (tests/golden/large_dt_512_sample.npz,
@@ -255,17 +274,21 @@ def test_large_dT_cavity_512_against_the_oracle(storage):
                     "--golden tests/golden/large_dt_512_sample.npz")
     z = np.load(path)
     stride, off, steps = int(z["stride"]), int(z["offset"]), int(z["time"])
+    arith = "f64" if storage.endswith("fp64-arith") else "f32"
+    storage = storage.split("-")[0]
     p = W.cavity(512, 1e5, 1.2, 0.06, sutherland=True, storage=storage)
     p.update(s_e=1.5, s_zeta=1.5)
-    print(f"[case] large-dT cavity 512x512 {storage}, {steps} steps, every {stride}th node", flush=True)
-    s = lbddf.Solver(p).init(*W.conduction_fields(p)).step(steps)
+    print(f"[case] large-dT cavity 512x512 {storage} storage, {arith} arithmetic, {steps} steps, every {stride}th "
+          "node", flush=True)
+    s = lbddf.Solver(p, arith=arith).init(*W.conduction_fields(p)).step(steps)
     g = tuple(a[off::stride, off::stride] for a in s.macros())
     e = rel_errors(g, (z["rho"], z["ux"], z["uy"], z["T"]))
     print(f"       rel err rho {e[0]:.3e} u {e[1]:.3e} T {e[2]:.3e}", flush=True)
     if storage == "f32":
-        assert max(e) < 5e-4, e
+        assert max(e) < (2e-5 if arith == "f64" else 5e-4), e
     if max(e) > TOL[storage]:
-        pytest.xfail(f"{storage} storage misses {TOL[storage]:g} on O(1) deviations from rest: errors {e}")
+        pytest.xfail(f"{storage} storage, {arith} arithmetic misses {TOL[storage]:g} on O(1) deviations from rest: "
+                     f"errors {e}")
 
 
 def test_large_dT_cavity_512_heat_balance_and_storage():
