@@ -15,6 +15,13 @@
  * Units: lattice units, dx = dt = c = 1, so R * T0 must equal 1/3 (Sec. II,
  * Sec. IV-A); lb_create rejects other values.
  *
+ * Arithmetic: liblbddf.so computes the step in FP32.  liblbddf_fp64.so, built
+ * from the same source, exports the same ABI with the step's arithmetic in
+ * FP64 and the same storage formats and state layout (about half the
+ * throughput; for flows whose FP32 rounding of large deviations from rest,
+ * such as a gravity-stratified cavity, exceeds what a result can tolerate).
+ * A state created by one library must be stepped by the same one.
+ *
  * Memory: the caller owns one device buffer of lb_state_bytes() bytes
  * (256-byte aligned) and keeps it alive until lb_destroy.  The library
  * allocates no device memory; it keeps only host-side state.  All device work
