@@ -17,10 +17,11 @@
  *
  * Arithmetic: liblbddf.so computes the step in FP32.  liblbddf_fp64.so, built
  * from the same source, exports the same ABI with the step's arithmetic in
- * FP64 and the same storage formats and state layout (about half the
- * throughput; for flows whose FP32 rounding of large deviations from rest,
- * such as a gravity-stratified cavity, exceeds what a result can tolerate).
- * A state created by one library must be stepped by the same one.
+ * FP64 and the same storage formats and state layout; its FP32 stores round
+ * stochastically (about half the throughput; for flows whose FP32 rounding
+ * of large deviations from rest, such as a gravity-stratified cavity,
+ * exceeds what a result can tolerate).  A state created by one library must
+ * be stepped by the same one.
  *
  * Memory: the caller owns one device buffer of lb_state_bytes() bytes
  * (256-byte aligned) and keeps it alive until lb_destroy.  The library

@@ -178,9 +178,26 @@ template <> struct Codec<LB_STORE_F32> {
         const Rsrc r = q < 9 ? P.f : P.h;
         return (real)__builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, vo, (q % 9) * P.pb, 0));
     }
-    static __device__ __forceinline__ void st(const Planes &P, unsigned vo, real v, int q, unsigned) {
+    static __device__ __forceinline__ void st(const Planes &P, unsigned vo, real v, int q, unsigned rb) {
         const Rsrc r = q < 9 ? P.f : P.h;
+#ifdef LB_ARITH_FP64
+        // The FP64 value rounds stochastically to FP32: one step past the
+        // round-to-nearest value f, towards v, with probability
+        // |v - f| / (that step), so that the storage adds no systematic
+        // drift to long runs (the random bits are the 24 high ones of rb)
+        float f = (float)v;
+        const real e = v - (real)f;
+        if (e != real(0.) && f != 0.f) {
+            const unsigned fb = __float_as_uint(f);
+            const float g = __uint_as_float(((e > real(0.)) == (f > 0.f)) ? fb + 1u : fb - 1u);
+            const real step = fabs((real)g - (real)f);
+            if (fabs(e) > (real)(rb >> 8) * real(1. / 16777216.) * step) f = g;
+        }
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(f), r, vo, (q % 9) * P.pb, kNT);
+#else
+        (void)rb;
         __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, (float)v), r, vo, (q % 9) * P.pb, kNT);
+#endif
     }
 };
 // FP16 keeps deviation * 2^(8 + k_a), k_a = 1, 3, 5 for the rest, axis and
@@ -686,7 +703,11 @@ __device__ __forceinline__ void collide_store(const KArgs &a, const Planes &D, c
     real o[18];
     collide<F>(a, d, m, kind, phix, phiy, o);
     if (owned) {
+#ifdef LB_ARITH_FP64
+        const unsigned h = hash32((vo / Codec<ST>::bytes) ^ (step * 0x9E3779B9u));  // FP32 stores round stochastically
+#else
         const unsigned h = ST == LB_STORE_F32 ? 0u : hash32((vo / Codec<ST>::bytes) ^ (step * 0x9E3779B9u));
+#endif
 #pragma unroll
         for (int q = 0; q < 18; ++q) Codec<ST>::st(D, vo, o[q], q, plane_bits(h, q));
     }
