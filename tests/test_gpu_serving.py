@@ -58,16 +58,18 @@ def test_server_matches_single_grid(gpu):
         assert max(e_srv) < TOL["f32"] and max(e_one) < TOL["f32"]
 
 
-@pytest.mark.parametrize("storage,target", [("f32", 1), ("f16", 1), ("f32", 4), ("f16", 4)])
-def test_alone_and_in_the_mix_are_identical(gpu, storage, target):
+@pytest.mark.parametrize("storage,target,arith", [("f32", 1, "f32"), ("f16", 1, "f32"), ("f32", 4, "f32"),
+                                                  ("f16", 4, "f32"), ("f32", 1, "f64"), ("f32", 4, "f64")])
+def test_alone_and_in_the_mix_are_identical(gpu, storage, target, arith):
     """Bit for bit, also with FP16 storage, whose stochastic rounding draws on
-    the node's index within its grid and the time step only; target 1 is a
-    narrow grid, 4 a wide one (block items with FP32 storage)."""
+    the node's index within its grid and the time step only, and on the
+    FP64-arithmetic library (stochastic FP32 stores); target 1 is a narrow
+    grid, 4 a wide one (block items with FP32 storage)."""
     reqs = _requests()
-    alone = lbddf.Server(_pool(reqs), storage=storage, k_steps=50)
+    alone = lbddf.Server(_pool(reqs), storage=storage, k_steps=50, arith=arith)
     a = alone.submit(reqs[target][0], _fields(*reqs[target]), tol=0.0, max_steps=400)
     _run_to_end(alone)
-    mixed = lbddf.Server(_pool(reqs), storage=storage, k_steps=50)
+    mixed = lbddf.Server(_pool(reqs), storage=storage, k_steps=50, arith=arith)
     ids = [mixed.submit(p, _fields(p, k), tol=0.0, max_steps=400 if i == target else 200 + 100 * i)
            for i, (p, k) in enumerate(reqs)]
     _run_to_end(mixed)
