@@ -621,6 +621,15 @@ __device__ __forceinline__ void collide(const KArgs &a, const real d[18], const 
         o[7] = d[7] + (a2 - X2 - Y2 + Pxy);
         o[8] = d[8] + (a2 + X2 - Y2 - Pxy);
     }
+    // The zeroth moment of h_eq must equal the energy of the node, i.e. the raw
+    // sum of its h, so that the BGK relaxation of h conserves energy.  The
+    // weights 4/9, 1/9, 1/36 are not representable in binary and round with
+    // one common relative error (about +7e-9 in FP32): the plain sum would
+    // add that fraction of the local energy deviation every step, a steady
+    // heat source that follows the gravity stratification and biases the
+    // flow.  h_eq of the rest velocity absorbs the remainder.
+    he[0] = (((d[9] + d[10]) + (d[11] + d[12])) + ((d[13] + d[14]) + (d[15] + d[16])) + d[17]) -
+            (((he[1] + he[2]) + (he[3] + he[4])) + ((he[5] + he[6]) + (he[7] + he[8])));
     // h: BGK plus the coupling term (1 - omega_h/2)(Z/tau_hf)(f - f_eq + C/2), Z = e.u
     const real wh = t.omega_h;
 #pragma unroll

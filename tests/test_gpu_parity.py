@@ -84,14 +84,14 @@ def test_paper_couette_power_law_adiabatic(gpu):
     _check(e, "f32")
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
-def test_cavity_small_dT(gpu, storage):
-    # tau_f = 0.56 as in the 128^2 case (0.536 is unstable in the oracle itself).
-    # 1000 steps: beyond that the FP32 rounding floor of this strongly
-    # stratified flow (absolute velocity error ~4e-7 against a decaying
-    # velocity scale) exceeds 1e-5 relative; see the long-horizon record.
+@pytest.mark.parametrize("storage,steps", [("f32", 12000), ("f16", 1000)])
+def test_cavity_small_dT(gpu, storage, steps):
+    """Gravity-driven small-dT cavity, tau_f = 0.56 as in the 128^2 case
+    (0.536 is unstable in the oracle itself).  FP32 storage over 12,000 steps
+    (measured 1.7e-7 / 3.6e-6 / 1.2e-7; the full convergence run is in the
+    validation tests); FP16 storage over 1000 steps."""
     p = W.cavity(70, 1e4, 0.02, 0.02, storage=storage)
-    _, _, _, _, e = run_pair(p, W.noisy_temperature_fields(p), 1000, "cavity small dT")
+    _, _, _, _, e = run_pair(p, W.noisy_temperature_fields(p), steps, "cavity small dT")
     _check(e, storage)
 
 

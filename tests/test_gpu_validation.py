@@ -129,13 +129,14 @@ def test_small_dT_cavity_table_ii_other_rows(Ra, n, mu_r, cap):
 
 def test_small_dT_cavity_converged_state_against_the_oracle():
     """Config 2 run 268,000 steps (its convergence above) on the GPU and in the
-    FP64 oracle.  rho and T meet the FP32 bar and the Table II quantities agree
-    to 1e-3; the velocity does not meet 1e-5: the flow's velocity (about
-    3.5e-3) is driven by a buoyancy 50 times smaller than the hydrostatic
-    forces (dT/T0 = 0.02), and FP32 rounding accumulates over the viscous
-    time H^2/nu of some 8e5 steps (measured: 5e-4).  The same run with the
-    step's arithmetic in FP64 (liblbddf_fp64.so, FP32 storage) meets 1e-5 in
-    all three (measured 1e-8 / 5e-7 / 1e-8)."""
+    FP64 oracle: FP32 arithmetic with FP32 storage within 1e-5 in rho, u and
+    T (measured 1.3e-7 / 5.0e-6 / 7.9e-8), and the Table II quantities agree
+    to 1e-4.  This flow's velocity (about 3.5e-3) is driven by a buoyancy
+    fifty times smaller than the hydrostatic forces (dT/T0 = 0.02), so a
+    steady per-step bias of the energy balance shows up in u: before the
+    zeroth moment of h_eq was closed on the node's energy, the rounding of the
+    lattice weights added such a bias and u was off by 5e-4.  The FP64-
+    arithmetic library meets the bar as well."""
     from oracle import oracle as O
 
     p = W.cavity(128, 1e4, 0.02, 0.02)
@@ -152,12 +153,10 @@ def test_small_dT_cavity_converged_state_against_the_oracle():
     mg, mr = P.cavity_metrics(p, *g[1:]), P.cavity_metrics(p, *r[1:])
     print(f"       rel err rho {e[0]:.3e} u {e[1]:.3e} T {e[2]:.3e}; Nu {mg['Nu']:.5f} / {mr['Nu']:.5f}, "
           f"u_max {mg['u_max']:.4f} / {mr['u_max']:.4f}, v_max {mg['v_max']:.4f} / {mr['v_max']:.4f}", flush=True)
-    assert e[0] < 2e-5 and e[2] < 2e-5, e
+    assert max(e) < TOL["f32"], e
     for k in ("Nu", "u_max", "v_max"):
-        assert abs(mg[k] / mr[k] - 1) < 1e-3, (k, mg[k], mr[k])
+        assert abs(mg[k] / mr[k] - 1) < 1e-4, (k, mg[k], mr[k])
     assert mg["y_max"] == mr["y_max"] and mg["x_max"] == mr["x_max"]
-    if max(e) > TOL["f32"]:
-        pytest.xfail(f"FP32 misses 1e-5 on the converged gravity-driven flow: errors {e}")
 
 
 def _beta_eq56(mu, Pr, b, period):
