@@ -70,6 +70,9 @@
 #define NQ 9
 #define DIM 2
 #define NPOP 18
+/* Grids smaller than this run their passes on one thread: a thread team's
+ * start-up and barriers would cost more than the work of a small grid. */
+#define ORC_OMP_MIN_NODES 8192
 
 enum { ORC_PERIODIC = 0, ORC_WALL = 1, ORC_ADIABATIC = 2, ORC_INLET = 3, ORC_OUTLET = 4 };
 enum { ORC_TOTAL = 0, ORC_INTERNAL = 1 };
@@ -342,7 +345,7 @@ static int classify(const orc_grid *g, int i, int j, int *fi, int *fj, int *sx, 
 static size_t nid(const orc_grid *g, int i, int j) { return (size_t)j * g->nx + i; }
 
 static void stage_moments(orc_grid *g) {
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (g->nx * g->ny >= ORC_OMP_MIN_NODES)
     for (int j = 0; j < g->ny; ++j)
         for (int i = 0; i < g->nx; ++i) {
             const size_t k = nid(g, i, j);
@@ -519,7 +522,7 @@ static void stage_collide(orc_grid *g) {
         g->Qy[k] = g->rho[k] * g->uy[k] * (1.0 - th);
     }
     const int corr = use_correction(g);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (g->nx * g->ny >= ORC_OMP_MIN_NODES)
     for (int j = 0; j < g->ny; ++j)
         for (int i = 0; i < g->nx; ++i) {
             int fi, fj, sx, sy;
@@ -544,7 +547,7 @@ static void stage_stream(orc_grid *g) {
     for (size_t k = 0; k < n; ++k) g->pop[k] = NAN;
     const int perx = !side_active(g, 0) && !side_active(g, 1);
     const int pery = !side_active(g, 2) && !side_active(g, 3);
-#pragma omp parallel for schedule(static)
+#pragma omp parallel for schedule(static) if (g->nx * g->ny >= ORC_OMP_MIN_NODES)
     for (int j = 0; j < g->ny; ++j)
         for (int i = 0; i < g->nx; ++i) {
             const double *src = g->post + nid(g, i, j) * NPOP;

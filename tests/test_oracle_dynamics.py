@@ -313,3 +313,46 @@ def test_applied_correction_meets_eq28_on_the_grid():
     for w in (np.ones(9), ex * 1.0, ey * 1.0, ex * ey * 1.0):
         assert np.abs(mom(w)).max() < 1e-15
     assert np.abs(dQx).max() > 1e-6
+
+
+def test_residual_matches_its_definition_on_known_fields():
+    """orc_residual returns ||T - T_snap||_2 / ||T||_2 against the last
+    snapshot, +inf before the first one.  Known fields: a uniform state at
+    T_a, then (populations swapped in) a field at T_b on half of the nodes and
+    T_a on the rest, so the residual is sqrt(n/2) |T_b - T_a| / sqrt(n/2
+    (T_a^2 + T_b^2)) in closed form; a repeated call without a change gives
+    exactly 0."""
+    p = W.periodic(8, 6)
+    Ta, Tb = 1.0, 1.25
+    o = O.Oracle(p).init(T=np.full((6, 8), Ta))
+    assert np.isinf(o.residual(update=True))
+    assert o.residual(update=False) == 0.0
+    T2 = np.full((6, 8), Ta)
+    T2[:3] = Tb
+    pops = O.Oracle(p).init(T=T2).pops()
+    o.set_pops(pops)
+    r = o.residual(update=True)
+    assert abs(r - abs(Tb - Ta) / math.sqrt(Ta * Ta + Tb * Tb)) < 1e-14, r
+    assert o.residual(update=True) == 0.0
+
+
+def test_diag_counts_non_finite_and_non_positive_nodes():
+    """orc_diag's last entry counts the nodes whose moments are non-finite or
+    whose density or temperature is not positive: one NaN population, then a
+    node with negative density, then both, on an otherwise uniform grid."""
+    p = W.periodic(7, 5)
+    o = O.Oracle(p).init()
+    assert o.diag()["bad"] == 0
+    base = o.pops()
+    nan = base.copy()
+    nan[4, 2, 3] = np.nan
+    o.set_pops(nan)
+    assert o.diag()["bad"] == 1
+    neg = base.copy()
+    neg[:9, 1, 1] *= -1.0
+    o.set_pops(neg)
+    assert o.diag()["bad"] == 1
+    both = neg.copy()
+    both[4, 2, 3] = np.nan
+    o.set_pops(both)
+    assert o.diag()["bad"] == 2

