@@ -138,8 +138,15 @@ lb_status lb_create(const lb_params *p, void *dev_state, size_t bytes, void *hip
  * Resets the time counter to 0 and forgets the temperature snapshot. */
 lb_status lb_init(lb_handle *h, const double *rho, const double *ux, const double *uy, const double *T);
 
-/* Advances n time steps (n >= 0), asynchronously on the stream. */
+/* Advances n time steps (n >= 0), asynchronously on the stream.  Whole
+ * batches of k steps (lb_set_graph_steps, default 32) replay a hipGraph of
+ * k step launches captured on first use for the state's current buffer; the
+ * rest are launched one by one.  Both give the same results bit for bit. */
 lb_status lb_step(lb_handle *h, long n);
+
+/* Launches per captured graph of lb_step: an even number up to 4096, or 0 to
+ * launch every step from the host.  LB_EINVAL otherwise. */
+lb_status lb_set_graph_steps(lb_handle *h, int k);
 
 /* Current time step n. */
 long lb_time(const lb_handle *h);
@@ -210,7 +217,7 @@ const char *lb_last_error(void);
  * each batch, so a request runs to the next multiple of k) or became unstable,
  * stores their final fields on the host, frees their memory and admits
  * waiting requests.
- * Requests of one server share its storage type; inlet sides are not served.
+ * Requests of one server share its storage type.
  * One server must not be used by two threads at once.
  * ------------------------------------------------------------------------ */
 typedef struct lbs_server lbs_server;

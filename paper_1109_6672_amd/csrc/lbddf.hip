@@ -83,6 +83,7 @@ struct KArgs {
     long long plane_bytes;  // a half (f or h) spans 9 plane_bytes
     unsigned pstride;       // bytes from one population's row to the next one's
     int total, heat, corr, coupled, bgk, visc, rho_press, has_force;
+    int dither;  // dithered FP32 sums in the bounded step (internal-energy grids)
     real rho0, E0, inv_E0, half_g, g, Pr;
     // relaxation for a constant tau_f
     real s_nu, s_e, s_z, s_q, s_rho, s_j, omega_h, kcoup;
@@ -92,8 +93,11 @@ struct KArgs {
     // sides x-, x+, y-, y+
     int side_kind[4];
     real side_ux[4], side_uy[4], side_dth[4];
-    // inlet state and time step of the launch
-    real in_drho, in_ux, in_dth;
+    // inlet source (Eq. 53-54): amplitudes of u_x, rho - rho0 and theta - 1,
+    // and 1 / period (steps); the phase comes from the time step on the device
+    real in_u, in_rho, in_th;
+    double in_rate;
+    // time step of the state a launch reads (modulo 2^32)
     unsigned step;
 };
 
@@ -119,13 +123,27 @@ struct Head {
 #define F_BGK (F::fixed ? F::bgk : (bool)a.bgk)
 #define F_CTAU (F::fixed ? F::ctau : (a.visc == LB_VISC_CONST_TAU))
 
-#ifndef LB_ARITH_FP64
-__device__ __forceinline__ real frcp(real x) {
-    const real r = __builtin_amdgcn_rcpf(x);
-    return fma(r, fma(-x, r, real(1.)), r);
+__device__ __forceinline__ float frcp(float x) {
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.f), r);
 }
+#ifdef LB_ARITH_FP64
+__device__ __forceinline__ double frcp(double x) { return 1.0 / x; }
 #else
-__device__ __forceinline__ real frcp(real x) { return real(1.) / x; }
+// FP64 reciprocal for the FP64 moments of the bounded-grid step: hardware
+// estimate plus two Newton steps
+__device__ __forceinline__ double frcp(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+#endif
+
+// sin(pi x) in the arithmetic type
+#ifndef LB_ARITH_FP64
+__device__ __forceinline__ real sin_pi(real x) { return sinpif(x); }
+#else
+__device__ __forceinline__ real sin_pi(real x) { return sinpi(x); }
 #endif
 
 // readlane of a real (two 32-bit halves in FP64)
@@ -251,9 +269,23 @@ template <> struct Codec<LB_STORE_BF16> {
 // u, dth = theta - 1; sf, sx, sy are the raw sums sum f, sum e f of the
 // (possibly rebuilt) populations, which equal drho, jx and jy + rho g / 2 on
 // interior nodes.
-struct Mom {
-    real drho, rho, jx, jy, ux, uy, dth, sf, sx, sy;
+template <class T> struct MomT {
+    T drho, rho, jx, jy, ux, uy, dth, sf, sx, sy;
 };
+typedef MomT<real> Mom;
+
+// Type of the moments and of the moment-space non-equilibrium of a node.
+// Bounded grids (walls, inlet, outlet) with FP32 storage compute them, and the
+// rebuild of their boundary nodes, in FP64: there the populations deviate from
+// the rest state by O(1) (large temperature differences, gravity
+// stratification), and FP32 rounding of the sums and of the cancellation
+// m - m_eq, repeated alike every step, biases the mass that the walls exchange
+// and the flow over long runs.  On CDNA4 an FP64 FMA issues at the rate of a
+// (non-packed) FP32 one; the cost is registers.  With 16-bit storage the
+// rounding of the stored values dominates and FP32 suffices.
+template <bool P> struct MomType { typedef real type; };
+template <> struct MomType<true> { typedef double type; };
+template <int ST, bool BC> constexpr bool kPrecise = BC && ST == LB_STORE_F32;
 
 // Pull-gather (Eq. 45): population a of node (x, y) is the post-collision
 // value stored at (x, y) - e_a, with periodic wrap.  Sources of a bounded
@@ -278,26 +310,44 @@ __device__ __forceinline__ void gather(const KArgs &a, const Planes &S, int x, i
 
 // Eq. 46 with the forcing note (rho u = sum e f + a/2, a = (0, -rho g)) and
 // Eq. 37 / the internal-energy form, written for deviations from rest.
-template <class F>
-__device__ __forceinline__ Mom moments(const KArgs &a, const real d[18]) {
-    Mom m;
-    const real s1 = (d[1] + d[3]) + (d[2] + d[4]);
-    const real s2 = (d[5] + d[7]) + (d[6] + d[8]);
+template <class F, class T = real>
+__device__ __forceinline__ MomT<T> moments(const KArgs &a, const real dr[18]) {
+    MomT<T> m;
+    T d[18];
+#pragma unroll
+    for (int q = 0; q < 18; ++q) d[q] = (T)dr[q];
+    const T s1 = (d[1] + d[3]) + (d[2] + d[4]);
+    const T s2 = (d[5] + d[7]) + (d[6] + d[8]);
     m.drho = d[0] + (s1 + s2);
-    const real jx = (d[1] - d[3]) + (d[5] - d[7]) + (d[8] - d[6]);
-    const real jy = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
+    const T jx = (d[1] - d[3]) + (d[5] - d[7]) + (d[8] - d[6]);
+    const T jy = (d[2] - d[4]) + (d[5] - d[7]) + (d[6] - d[8]);
     m.sf = m.drho;
     m.sx = jx;
     m.sy = jy;
-    m.rho = a.rho0 + m.drho;
-    const real ir = frcp(m.rho);
+    m.rho = (T)a.rho0 + m.drho;
+    const T ir = frcp(m.rho);
     m.jx = jx;
-    m.jy = F_FORCE ? jy - a.half_g * m.rho : jy;
+    m.jy = F_FORCE ? jy - (T)a.half_g * m.rho : jy;
     m.ux = m.jx * ir;
     m.uy = m.jy * ir;
-    const real sh = ((d[9] + d[10]) + (d[11] + d[12])) + ((d[13] + d[14]) + (d[15] + d[16])) + d[17];
-    const real e = (sh - m.drho * a.E0) * ir;  // E - E0 (total) or (rho E_int - rho E0)/rho
-    m.dth = F_TOTAL ? (e - real(0.5) * (m.ux * m.ux + m.uy * m.uy)) * a.inv_E0 : e * a.inv_E0;
+    const T sh = ((d[9] + d[10]) + (d[11] + d[12])) + ((d[13] + d[14]) + (d[15] + d[16])) + d[17];
+    const T e = (sh - m.drho * (T)a.E0) * ir;  // E - E0 (total) or (rho E_int - rho E0)/rho
+    m.dth = F_TOTAL ? (e - T(0.5) * (m.ux * m.ux + m.uy * m.uy)) * (T)a.inv_E0 : e * (T)a.inv_E0;
+    return m;
+}
+
+template <class T, class U> __device__ __forceinline__ MomT<T> mom_cast(const MomT<U> &u) {
+    MomT<T> m;
+    m.drho = (T)u.drho;
+    m.rho = (T)u.rho;
+    m.jx = (T)u.jx;
+    m.jy = (T)u.jy;
+    m.ux = (T)u.ux;
+    m.uy = (T)u.uy;
+    m.dth = (T)u.dth;
+    m.sf = (T)u.sf;
+    m.sx = (T)u.sx;
+    m.sy = (T)u.sy;
     return m;
 }
 
@@ -306,47 +356,47 @@ __device__ __forceinline__ Mom moments(const KArgs &a, const real d[18]) {
 // j = rho u so that the first moment of f_eq is j itself:
 //   f_eq - f_rest = w [drho + c rho th - 1.5 j.u + (e.j)(B + 4.5 e.u)],
 //   c = -1, 1/2, 2 and B = 3, 3 - 1.5 th, 3 + 3 th for |e|^2 = 0, 1, 2.
-template <class F>
-__device__ __forceinline__ void equilibria(const KArgs &a, const Mom &m, real fe[9], real he[9]) {
-    const real w0 = real(4.) / real(9.), w1 = real(1.) / real(9.), w2 = real(1.) / real(36.);
-    const real th = F_COUPLED ? m.dth : real(0.);  // theta_eq - 1
-    const real ux = m.ux, uy = m.uy, jx = m.jx, jy = m.jy, drho = m.drho, rho = m.rho;
-    const real ju = jx * ux + jy * uy;
-    const real base = drho - real(1.5) * ju;
-    const real rth = rho * th;
-    const real A0 = base - rth, A1 = base + real(0.5) * rth, A2 = base + real(2.) * rth;
-    const real B1 = real(3.) - real(1.5) * th, B2 = real(3.) + real(3.) * th;
-    const real v5 = ux + uy, v6 = uy - ux, j5 = jx + jy, j6 = jy - jx;
+template <class F, class T>
+__device__ __forceinline__ void equilibria(const KArgs &a, const MomT<T> &m, T fe[9], T he[9]) {
+    const T w0 = T(4.) / T(9.), w1 = T(1.) / T(9.), w2 = T(1.) / T(36.);
+    const T th = F_COUPLED ? m.dth : T(0.);  // theta_eq - 1
+    const T ux = m.ux, uy = m.uy, jx = m.jx, jy = m.jy, drho = m.drho, rho = m.rho;
+    const T ju = jx * ux + jy * uy;
+    const T base = drho - T(1.5) * ju;
+    const T rth = rho * th;
+    const T A0 = base - rth, A1 = base + T(0.5) * rth, A2 = base + T(2.) * rth;
+    const T B1 = T(3.) - T(1.5) * th, B2 = T(3.) + T(3.) * th;
+    const T v5 = ux + uy, v6 = uy - ux, j5 = jx + jy, j6 = jy - jx;
     fe[0] = w0 * A0;
-    fe[1] = w1 * (A1 + jx * (B1 + real(4.5) * ux));
-    fe[3] = w1 * (A1 - jx * (B1 - real(4.5) * ux));
-    fe[2] = w1 * (A1 + jy * (B1 + real(4.5) * uy));
-    fe[4] = w1 * (A1 - jy * (B1 - real(4.5) * uy));
-    fe[5] = w2 * (A2 + j5 * (B2 + real(4.5) * v5));
-    fe[7] = w2 * (A2 - j5 * (B2 - real(4.5) * v5));
-    fe[6] = w2 * (A2 + j6 * (B2 + real(4.5) * v6));
-    fe[8] = w2 * (A2 - j6 * (B2 - real(4.5) * v6));
-    const real u2 = ux * ux + uy * uy;
+    fe[1] = w1 * (A1 + jx * (B1 + T(4.5) * ux));
+    fe[3] = w1 * (A1 - jx * (B1 - T(4.5) * ux));
+    fe[2] = w1 * (A1 + jy * (B1 + T(4.5) * uy));
+    fe[4] = w1 * (A1 - jy * (B1 - T(4.5) * uy));
+    fe[5] = w2 * (A2 + j5 * (B2 + T(4.5) * v5));
+    fe[7] = w2 * (A2 - j5 * (B2 - T(4.5) * v5));
+    fe[6] = w2 * (A2 + j6 * (B2 + T(4.5) * v6));
+    fe[8] = w2 * (A2 - j6 * (B2 - T(4.5) * v6));
+    const T u2 = ux * ux + uy * uy;
     if (F_TOTAL) {
         // h_eq - h_rest = w [rho0 (E - E0) + c (p theta - p0) + p (3 eu + 9 eu^2 - 3 u^2)] + E (f_eq - f_rest),
         // p (3 eu + 9 eu^2 - 3 u^2) = theta [(e.j)(1 + 3 e.u) - j.u] with p = rho theta / 3
-        const real E = a.E0 * (real(1.) + m.dth) + real(0.5) * u2;
-        const real K0 = a.rho0 * (a.E0 * m.dth + real(0.5) * u2);
-        const real third = real(1.) / real(3.);
-        const real Pt = real(1.) + th;
-        const real Pd = (drho + rth * (real(2.) + th)) * third;
-        const real k0 = K0 - Pd - Pt * ju, k1 = K0 + real(0.5) * Pd - Pt * ju, k2 = K0 + real(2.) * Pd - Pt * ju;
+        const T E = (T)a.E0 * (T(1.) + m.dth) + T(0.5) * u2;
+        const T K0 = (T)a.rho0 * ((T)a.E0 * m.dth + T(0.5) * u2);
+        const T third = T(1.) / T(3.);
+        const T Pt = T(1.) + th;
+        const T Pd = (drho + rth * (T(2.) + th)) * third;
+        const T k0 = K0 - Pd - Pt * ju, k1 = K0 + T(0.5) * Pd - Pt * ju, k2 = K0 + T(2.) * Pd - Pt * ju;
         he[0] = w0 * k0 + E * fe[0];
-        he[1] = w1 * (k1 + Pt * jx * (real(1.) + real(3.) * ux)) + E * fe[1];
-        he[3] = w1 * (k1 - Pt * jx * (real(1.) - real(3.) * ux)) + E * fe[3];
-        he[2] = w1 * (k1 + Pt * jy * (real(1.) + real(3.) * uy)) + E * fe[2];
-        he[4] = w1 * (k1 - Pt * jy * (real(1.) - real(3.) * uy)) + E * fe[4];
-        he[5] = w2 * (k2 + Pt * j5 * (real(1.) + real(3.) * v5)) + E * fe[5];
-        he[7] = w2 * (k2 - Pt * j5 * (real(1.) - real(3.) * v5)) + E * fe[7];
-        he[6] = w2 * (k2 + Pt * j6 * (real(1.) + real(3.) * v6)) + E * fe[6];
-        he[8] = w2 * (k2 - Pt * j6 * (real(1.) - real(3.) * v6)) + E * fe[8];
+        he[1] = w1 * (k1 + Pt * jx * (T(1.) + T(3.) * ux)) + E * fe[1];
+        he[3] = w1 * (k1 - Pt * jx * (T(1.) - T(3.) * ux)) + E * fe[3];
+        he[2] = w1 * (k1 + Pt * jy * (T(1.) + T(3.) * uy)) + E * fe[2];
+        he[4] = w1 * (k1 - Pt * jy * (T(1.) - T(3.) * uy)) + E * fe[4];
+        he[5] = w2 * (k2 + Pt * j5 * (T(1.) + T(3.) * v5)) + E * fe[5];
+        he[7] = w2 * (k2 - Pt * j5 * (T(1.) - T(3.) * v5)) + E * fe[7];
+        he[6] = w2 * (k2 + Pt * j6 * (T(1.) + T(3.) * v6)) + E * fe[6];
+        he[8] = w2 * (k2 - Pt * j6 * (T(1.) - T(3.) * v6)) + E * fe[8];
     } else {
-        const real c = a.rho0 * a.E0 * m.dth, Et = a.E0 * (real(1.) + m.dth);
+        const T c = (T)a.rho0 * (T)a.E0 * m.dth, Et = (T)a.E0 * (T(1.) + m.dth);
         he[0] = w0 * c + Et * fe[0];
 #pragma unroll
         for (int q = 1; q < 5; ++q) he[q] = w1 * c + Et * fe[q];
@@ -453,84 +503,129 @@ __device__ __forceinline__ void node_issue(const KArgs &a, const Planes &S, int 
     gather<ST>(a, S, b.fx, b.fy, d);
 }
 
+// On a bounded grid the rebuild runs in FP64 (MomType); a wall node hands its
+// FP64 density and temperature deviations to the collision in bw[0], bw[1].
 template <int ST, bool BC, class F>
-__device__ __forceinline__ int node_finish(const KArgs &a, const Planes &S, int x, int y, real d[18], Mom &m) {
+__device__ __forceinline__ int node_finish(const KArgs &a, const Planes &S, int x, int y, real d[18], Mom &m,
+                                           double bw[2], unsigned step) {
+    typedef typename MomType<kPrecise<ST, BC>>::type T;
     m = moments<F>(a, d);
     if (!BC) return K_INTERIOR;
     const BInfo b = classify(a, x, y);
     if (b.kind == K_INTERIOR || b.kind == K_OUTLET) return b.kind;  // outlet: exact copy of the neighbour
-    Mom mb;
+    MomT<T> mb;
     if (b.kind == K_INLET) {
-        mb.drho = a.in_drho;
-        mb.ux = a.in_ux;
-        mb.uy = real(0.);
-        mb.dth = a.in_dth;
-        mb.rho = a.rho0 + mb.drho;
-        mb.jx = mb.rho * mb.ux;
-        mb.jy = real(0.);
+        // s = sin(2 pi n / P) at the time n of the state (Eq. 53): the phase
+        // n / P reduced in FP64, the sine in the arithmetic type
+        const double t = (double)step * a.in_rate;
+        const real s = sin_pi(real(2.) * (real)(t - floor(t)));
+        m.drho = a.in_rho * s;
+        m.ux = a.in_u * s;
+        m.uy = real(0.);
+        m.dth = a.in_th * s;
+        m.rho = a.rho0 + m.drho;
+        m.jx = m.rho * m.ux;
+        m.jy = real(0.);
         real he[9];
-        equilibria<F>(a, mb, d, he);
+        equilibria<F>(a, m, d, he);
 #pragma unroll
         for (int q = 0; q < 9; ++q) d[9 + q] = he[q];
         const Mom raw = moments<F>(a, d);
-        mb.sf = raw.sf;
-        mb.sx = raw.sx;
-        mb.sy = raw.sy;
-        m = mb;
+        m.sf = raw.sf;
+        m.sx = raw.sx;
+        m.sy = raw.sy;
         return K_INLET;
     }
-    mb.ux = b.ux;
-    mb.uy = b.uy;
+    const MomT<T> mf = moments<F, T>(a, d);
+    mb.ux = (T)b.ux;
+    mb.uy = (T)b.uy;
     if (b.kind == K_DIRICHLET) {
-        mb.dth = b.dth;
+        mb.dth = (T)b.dth;
     } else {
         // T_b = (4 T_1 - T_2) / 3 along the inward normal
         real d2[18];
         gather<ST>(a, S, 2 * b.fx - x, 2 * b.fy - y, d2);
-        const Mom m2 = moments<F>(a, d2);
-        mb.dth = (real(4.) * m.dth - m2.dth) * (real(1.) / real(3.));
+        const MomT<T> m2 = moments<F, T>(a, d2);
+        mb.dth = (T(4.) * mf.dth - m2.dth) * (T(1.) / T(3.));
     }
     // pressure extrapolation with the hydrostatic balance of the body force,
     // p_b = p_f exp(x), x = g (y_f - y_b) / (R T_m), T_m = (T_f + T_b)/2
     // (R T0 = 1/3), i.e. rho_b = rho_f theta_f / theta_b (1 + expm1(x));
     // or density extrapolation rho_b = rho_f
     if (a.rho_press) {
-        const real x = real(6.) * a.g * (real)(b.fy - y) * frcp(real(2.) + m.dth + mb.dth);
-        const real em1 = x * (real(1.) + x * (real(0.5) + x * (real(1.) / real(6.) + x * (real(1.) / real(24.)))));
-        mb.drho = m.drho + m.rho * ((m.dth - mb.dth) + (real(1.) + m.dth) * em1) * frcp(real(1.) + mb.dth);
+        const T x = T(6.) * (T)a.g * (T)(b.fy - y) * frcp(T(2.) + mf.dth + mb.dth);
+        const T em1 = x * (T(1.) + x * (T(0.5) + x * (T(1.) / T(6.) + x * (T(1.) / T(24.)))));
+        mb.drho = mf.drho + mf.rho * ((mf.dth - mb.dth) + (T(1.) + mf.dth) * em1) * frcp(T(1.) + mb.dth);
     } else {
-        mb.drho = m.drho;
+        mb.drho = mf.drho;
     }
-    mb.rho = a.rho0 + mb.drho;
+    mb.rho = (T)a.rho0 + mb.drho;
     mb.jx = mb.rho * mb.ux;
     mb.jy = mb.rho * mb.uy;
-    real fb[9], hb[9], ff[9], hf[9];
+    T fb[9], hb[9], ff[9], hf[9];
     equilibria<F>(a, mb, fb, hb);
-    equilibria<F>(a, m, ff, hf);
+    equilibria<F>(a, mf, ff, hf);
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        d[q] += fb[q] - ff[q];
-        d[9 + q] += hb[q] - hf[q];
+        d[q] = (real)((T)d[q] + (fb[q] - ff[q]));
+        d[9 + q] = (real)((T)d[9 + q] + (hb[q] - hf[q]));
     }
     const Mom raw = moments<F>(a, d);
-    mb.sf = raw.sf;
-    mb.sx = raw.sx;
-    mb.sy = raw.sy;
-    m = mb;
+    m = mom_cast<real>(mb);
+    m.sf = raw.sf;
+    m.sx = raw.sx;
+    m.sy = raw.sy;
+    bw[0] = (double)mb.drho;
+    bw[1] = (double)mb.dth;
     return b.kind;
 }
 
 template <int ST, bool BC>
 __device__ __forceinline__ int node_state(const KArgs &a, const Planes &S, int x, int y, real d[18], Mom &m) {
     node_issue<ST, BC>(a, S, x, y, d);
-    return node_finish<ST, BC, Dyn>(a, S, x, y, d, m);
+    double bw[2];
+    return node_finish<ST, BC, Dyn>(a, S, x, y, d, m, bw, a.step);
 }
 
 // Collision of one node (Eq. 44 or Eq. 34 for f^, Eq. 47 or Eq. 38 for h-),
 // deviations in d, results in o.
-template <class F>
-__device__ __forceinline__ void collide(const KArgs &a, const real d[18], const Mom &m, int kind, real phix,
-                                        real phiy, real o[18]) {
+// plane_bits: defined with the counter hash below
+__device__ __forceinline__ unsigned plane_bits(unsigned h, int q);
+
+// d + inc in FP32 with a rounding that is unbiased on average: inc is dithered
+// by a uniform random fraction of one unit in the last place of d before the
+// sum rounds to nearest, so that repeated steps of a (nearly) steady state do
+// not accumulate the same rounding every step.  (When |inc| < |d| the
+// dithered sum rounds down or up with probabilities given by its position
+// between the two neighbours of the exact sum.)
+__device__ __forceinline__ float add_dithered(float d, float inc, unsigned bits) {
+    const float u = __uint_as_float(__float_as_uint(d) & 0x7f800000u) * 0x1p-23f;  // ulp of d (0 for 0)
+    const float r = __uint_as_float(0x3f800000u | (bits >> 9)) - 1.5f;               // uniform in [-1/2, 1/2)
+    return d + fmaf(r, u, inc);
+}
+#ifdef LB_ARITH_FP64
+__device__ __forceinline__ double add_dithered(double d, double inc, unsigned) { return d + inc; }
+#endif
+
+// The moment-space increments (Eq. 44) are formed in the moment type of the
+// grid (MomType), then applied in the arithmetic type.  On a bounded grid the
+// FP64 moments are the sums of the populations, except that a wall node takes
+// its FP64 density and temperature (bw) and its wall velocity.
+template <class F, bool PR>
+__device__ __forceinline__ void collide(const KArgs &a, const real d[18], const Mom &m, int kind, const double bw[2],
+                                        real phix, real phiy, real o[18], unsigned rb) {
+    typedef typename MomType<PR>::type T;
+    MomT<T> mt = moments<F, T>(a, d);
+    if (PR && (kind == K_DIRICHLET || kind == K_ADIABATIC)) {
+        mt.drho = (T)bw[0];
+        mt.dth = (T)bw[1];
+        mt.rho = (T)a.rho0 + mt.drho;
+        mt.ux = (T)m.ux;
+        mt.uy = (T)m.uy;
+        mt.jx = mt.rho * mt.ux;
+        mt.jy = mt.rho * mt.uy;
+    }
+    if (!PR) mt = mom_cast<T>(m);
     real fe[9], he[9];
     equilibria<F>(a, m, fe, he);
     if (kind == K_INLET) {
@@ -570,40 +665,45 @@ __device__ __forceinline__ void collide(const KArgs &a, const real d[18], const 
     {
         // BGK (Eq. 34) is the MRT scheme with every rate equal to 1/tau_f, so both
         // run through the same moment-space increments.
-        const real sr = F_BGK ? t.s_nu : a.s_rho, sj = F_BGK ? t.s_nu : a.s_j;
-        const real se = F_BGK ? t.s_nu : t.s_e, sz = F_BGK ? t.s_nu : t.s_z, sq = F_BGK ? t.s_nu : a.s_q;
+        const T sr = (T)(F_BGK ? t.s_nu : a.s_rho), sj = (T)(F_BGK ? t.s_nu : a.s_j);
+        const T se = (T)(F_BGK ? t.s_nu : t.s_e), sz = (T)(F_BGK ? t.s_nu : t.s_z);
+        const T sq = (T)(F_BGK ? t.s_nu : a.s_q), sn = (T)t.s_nu;
+        T dt[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) dt[q] = (T)d[q];
         // moments of the deviations, m = M f (Eq. B1); the conserved ones are
         // the raw sums, so that their increments vanish exactly on interior nodes
-        const real s1 = (d[1] + d[3]) + (d[2] + d[4]);
-        const real s2 = (d[5] + d[7]) + (d[6] + d[8]);
-        const real dx13 = d[1] - d[3], dy24 = d[2] - d[4];
-        const real a57 = d[5] - d[7], a86 = d[8] - d[6], a68 = d[6] - d[8];
-        const real m1 = -real(4.) * d[0] - s1 + real(2.) * s2;
-        const real m2 = real(4.) * d[0] - real(2.) * s1 + s2;
-        const real m4 = -real(2.) * dx13 + (a57 + a86);
-        const real m6 = -real(2.) * dy24 + (a57 + a68);
-        const real m7 = (d[1] + d[3]) - (d[2] + d[4]);
-        const real m8 = (d[5] + d[7]) - (d[6] + d[8]);
+        const T s1 = (dt[1] + dt[3]) + (dt[2] + dt[4]);
+        const T s2 = (dt[5] + dt[7]) + (dt[6] + dt[8]);
+        const T dx13 = dt[1] - dt[3], dy24 = dt[2] - dt[4];
+        const T a57 = dt[5] - dt[7], a86 = dt[8] - dt[6], a68 = dt[6] - dt[8];
+        const T m1 = -T(4.) * dt[0] - s1 + T(2.) * s2;
+        const T m2 = T(4.) * dt[0] - T(2.) * s1 + s2;
+        const T m4 = -T(2.) * dx13 + (a57 + a86);
+        const T m6 = -T(2.) * dy24 + (a57 + a68);
+        const T m7 = (dt[1] + dt[3]) - (dt[2] + dt[4]);
+        const T m8 = (dt[5] + dt[7]) - (dt[6] + dt[8]);
         // equilibria Eq. 41 minus M f_rest
-        const real thE = F_COUPLED ? m.dth : real(0.);
-        const real rho = m.rho;
-        const real qq = real(3.) * (m.jx * ux + m.jy * uy) + real(2.) * rho * thE;
-        const real e1 = -real(2.) * m.drho + qq, e2 = m.drho - qq;
-        const real e4 = -m.jx * (real(1.) - thE), e6 = -m.jy * (real(1.) - thE);
-        const real e7 = m.jx * ux - m.jy * uy, e8 = m.jx * uy;
+        const T thE = F_COUPLED ? mt.dth : T(0.);
+        const T uxt = mt.ux, uyt = mt.uy, ayt = -mt.rho * (T)a.g;
+        const T qq = T(3.) * (mt.jx * uxt + mt.jy * uyt) + T(2.) * mt.rho * thE;
+        const T e1 = -T(2.) * mt.drho + qq, e2 = mt.drho - qq;
+        const T e4 = -mt.jx * (T(1.) - thE), e6 = -mt.jy * (T(1.) - thE);
+        const T e7 = mt.jx * uxt - mt.jy * uyt, e8 = mt.jx * uyt;
         // sources C^ = (0, phi_x, 0, 0, 0, 0, 0, phi_y, 0) + F^ (Eq. 48, 51)
-        const real uay = uy * ay;
-        const real c1 = phix + real(6.) * uay, c2 = -real(6.) * uay, c5 = ay, c6 = -ay, c7 = phiy - real(2.) * uay, c8 = ux * ay;
+        const T uay = uyt * ayt;
+        const T c1 = (T)phix + T(6.) * uay, c2 = -T(6.) * uay, c5 = ayt, c6 = -ayt, c7 = (T)phiy - T(2.) * uay,
+                c8 = uxt * ayt;
         // Eq. 44 as increments dm = m* - m
-        const real g0 = -sr * (m.sf - m.drho);
-        const real g1 = -se * (m1 - e1) + (real(1.) - real(0.5) * se) * c1;
-        const real g2 = -sz * (m2 - e2) + (real(1.) - real(0.5) * sz) * c2;
-        const real g3 = -sj * (m.sx - m.jx);
-        const real g4 = -sq * (m4 - e4);
-        const real g5 = -sj * (m.sy - m.jy) + (real(1.) - real(0.5) * sj) * c5;
-        const real g6 = -sq * (m6 - e6) + (real(1.) - real(0.5) * sq) * c6;
-        const real g7 = -t.s_nu * (m7 - e7) + (real(1.) - real(0.5) * t.s_nu) * c7;
-        const real g8 = -t.s_nu * (m8 - e8) + (real(1.) - real(0.5) * t.s_nu) * c8;
+        const real g0 = (real)(-sr * (mt.sf - mt.drho));
+        const real g1 = (real)(-se * (m1 - e1) + (T(1.) - T(0.5) * se) * c1);
+        const real g2 = (real)(-sz * (m2 - e2) + (T(1.) - T(0.5) * sz) * c2);
+        const real g3 = (real)(-sj * (mt.sx - mt.jx));
+        const real g4 = (real)(-sq * (m4 - e4));
+        const real g5 = (real)(-sj * (mt.sy - mt.jy) + (T(1.) - T(0.5) * sj) * c5);
+        const real g6 = (real)(-sq * (m6 - e6) + (T(1.) - T(0.5) * sq) * c6);
+        const real g7 = (real)(-sn * (m7 - e7) + (T(1.) - T(0.5) * sn) * c7);
+        const real g8 = (real)(-sn * (m8 - e8) + (T(1.) - T(0.5) * sn) * c8);
         // f* = f + M^-1 dm (Eq. B2)
         const real A = g0 * (real(1.) / real(9.));
         const real a1 = A - g1 * (real(1.) / real(36.)) - g2 * (real(1.) / real(18.));
@@ -611,15 +711,15 @@ __device__ __forceinline__ void collide(const KArgs &a, const real d[18], const 
         const real X = (g3 - g4) * (real(1.) / real(6.)), Y = (g5 - g6) * (real(1.) / real(6.)), P = real(0.25) * g7;
         const real X2 = g3 * (real(1.) / real(6.)) + g4 * (real(1.) / real(12.)), Y2 = g5 * (real(1.) / real(6.)) + g6 * (real(1.) / real(12.));
         const real Pxy = real(0.25) * g8;
-        o[0] = d[0] + (A + (g2 - g1) * (real(1.) / real(9.)));
-        o[1] = d[1] + (a1 + X + P);
-        o[3] = d[3] + (a1 - X + P);
-        o[2] = d[2] + (a1 + Y - P);
-        o[4] = d[4] + (a1 - Y - P);
-        o[5] = d[5] + (a2 + X2 + Y2 + Pxy);
-        o[6] = d[6] + (a2 - X2 + Y2 - Pxy);
-        o[7] = d[7] + (a2 - X2 - Y2 + Pxy);
-        o[8] = d[8] + (a2 + X2 - Y2 - Pxy);
+        o[0] = (PR && a.dither) ? add_dithered(d[0], (A + (g2 - g1) * (real(1.) / real(9.))), plane_bits(rb, 0)) : d[0] + (A + (g2 - g1) * (real(1.) / real(9.)));
+        o[1] = (PR && a.dither) ? add_dithered(d[1], (a1 + X + P), plane_bits(rb, 1)) : d[1] + (a1 + X + P);
+        o[3] = (PR && a.dither) ? add_dithered(d[3], (a1 - X + P), plane_bits(rb, 3)) : d[3] + (a1 - X + P);
+        o[2] = (PR && a.dither) ? add_dithered(d[2], (a1 + Y - P), plane_bits(rb, 2)) : d[2] + (a1 + Y - P);
+        o[4] = (PR && a.dither) ? add_dithered(d[4], (a1 - Y - P), plane_bits(rb, 4)) : d[4] + (a1 - Y - P);
+        o[5] = (PR && a.dither) ? add_dithered(d[5], (a2 + X2 + Y2 + Pxy), plane_bits(rb, 5)) : d[5] + (a2 + X2 + Y2 + Pxy);
+        o[6] = (PR && a.dither) ? add_dithered(d[6], (a2 - X2 + Y2 - Pxy), plane_bits(rb, 6)) : d[6] + (a2 - X2 + Y2 - Pxy);
+        o[7] = (PR && a.dither) ? add_dithered(d[7], (a2 - X2 - Y2 + Pxy), plane_bits(rb, 7)) : d[7] + (a2 - X2 - Y2 + Pxy);
+        o[8] = (PR && a.dither) ? add_dithered(d[8], (a2 + X2 - Y2 - Pxy), plane_bits(rb, 8)) : d[8] + (a2 + X2 - Y2 - Pxy);
     }
     // The zeroth moment of h_eq must equal the energy of the node, i.e. the raw
     // sum of its h, so that the BGK relaxation of h conserves energy.  The
@@ -631,6 +731,27 @@ __device__ __forceinline__ void collide(const KArgs &a, const real d[18], const 
     he[0] = (((d[9] + d[10]) + (d[11] + d[12])) + ((d[13] + d[14]) + (d[15] + d[16])) + d[17]) -
             (((he[1] + he[2]) + (he[3] + he[4])) + ((he[5] + he[6]) + (he[7] + he[8])));
     // h: BGK plus the coupling term (1 - omega_h/2)(Z/tau_hf)(f - f_eq + C/2), Z = e.u
+    if (PR) {
+        // in the moment type: the equilibria and the non-equilibrium h - h_eq
+        // of O(1) deviations, with the same closure of the zeroth moment
+        T fT[9], hT[9];
+        equilibria<F>(a, mt, fT, hT);
+        T dh[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) dh[q] = (T)d[9 + q];
+        hT[0] = (((dh[0] + dh[1]) + (dh[2] + dh[3])) + ((dh[4] + dh[5]) + (dh[6] + dh[7])) + dh[8]) -
+                (((hT[1] + hT[2]) + (hT[3] + hT[4])) + ((hT[5] + hT[6]) + (hT[7] + hT[8])));
+        const T whT = (T)t.omega_h, kT = (T)t.kcoup;
+        const T v5 = mt.ux + mt.uy, v6 = mt.uy - mt.ux;
+        const T z[9] = {T(0.), mt.ux, mt.uy, -mt.ux, -mt.uy, v5, v6, -v5, -v6};
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            T inc = -whT * (dh[q] - hT[q]);
+            if (F_HEAT && q > 0) inc += kT * z[q] * ((T)d[q] - fT[q] + T(0.5) * (T)C[q]);
+            o[9 + q] = a.dither ? add_dithered(d[9 + q], (real)inc, plane_bits(rb, 9 + q)) : d[9 + q] + (real)inc;
+        }
+        return;
+    }
     const real wh = t.omega_h;
 #pragma unroll
     for (int q = 0; q < 9; ++q) o[9 + q] = d[9 + q] - wh * (d[9 + q] - he[q]);
@@ -686,10 +807,10 @@ __device__ __forceinline__ void row_issue(const KArgs &a, const Planes &S, int x
 // Moments, kind and Q = rho u (1 - theta) (Eq. 48) of the lane's node in row y.
 template <int ST, bool BC, class F>
 __device__ __forceinline__ int row_finish(const KArgs &a, const Planes &S, int xw, bool xin, int y, real d[18],
-                                          Mom &m, real &Qx, real &Qy) {
+                                          Mom &m, double bw[2], real &Qx, real &Qy, unsigned step) {
     bool yin;
     const int yw = row_wrap(a, y, yin);
-    const int kind = node_finish<ST, BC, F>(a, S, xw, yw, d, m);
+    const int kind = node_finish<ST, BC, F>(a, S, xw, yw, d, m, bw, step);
     const real mq = (F_CORR && xin && yin) ? -m.rho * m.dth : real(0.);
     Qx = mq * m.ux;
     Qy = mq * m.uy;
@@ -701,6 +822,7 @@ __device__ __forceinline__ int row_finish(const KArgs &a, const Planes &S, int x
 // halo values qhl, qhr), collision, store of the owned lanes.
 template <int ST, bool BC, class F>
 __device__ __forceinline__ void collide_store(const KArgs &a, const Planes &D, const real d[18], const Mom &m,
+                                              const double bw[2],
                                               int kind, int lane, real qxc, real qhl, real qhr, real qyp,
                                               real qyn, bool owned, unsigned vo, unsigned step) {
     real qxl = __shfl_up(qxc, 1), qxr = __shfl_down(qxc, 1);
@@ -710,13 +832,17 @@ __device__ __forceinline__ void collide_store(const KArgs &a, const Planes &D, c
     real phix = real(3.) * (dQx + dQy), phiy = dQx - dQy;
     if (BC && kind != K_INTERIOR) phix = phiy = real(0.);
     real o[18];
-    collide<F>(a, d, m, kind, phix, phiy, o);
-    if (owned) {
+    // random bits of the node and step: the stochastic rounding of the 16-bit
+    // codecs and of the FP64-arithmetic library's FP32 stores, the dithered
+    // sums of the bounded FP32 step
 #ifdef LB_ARITH_FP64
-        const unsigned h = hash32((vo / Codec<ST>::bytes) ^ (step * 0x9E3779B9u));  // FP32 stores round stochastically
+    constexpr bool need_bits = true;
 #else
-        const unsigned h = ST == LB_STORE_F32 ? 0u : hash32((vo / Codec<ST>::bytes) ^ (step * 0x9E3779B9u));
+    constexpr bool need_bits = ST != LB_STORE_F32 || kPrecise<ST, BC>;
 #endif
+    const unsigned h = need_bits ? hash32((vo / Codec<ST>::bytes) ^ (step * 0x9E3779B9u)) : 0u;
+    collide<F, kPrecise<ST, BC>>(a, d, m, kind, bw, phix, phiy, o, h);
+    if (owned) {
 #pragma unroll
         for (int q = 0; q < 18; ++q) Codec<ST>::st(D, vo, o[q], q, plane_bits(h, q));
     }
@@ -742,7 +868,7 @@ __device__ __forceinline__ int col_wrap(const KArgs &a, int x, bool &xin) {
 // serves 32 rows; the row loop picks its values out with readlane.
 template <int ST, bool BC, class F>
 __device__ __forceinline__ real halo_chunk(const KArgs &a, const Planes &S, int x0, int lane, int yb, int dir,
-                                            int ylo, int yhi, bool need_l, bool need_r) {
+                                            int ylo, int yhi, bool need_l, bool need_r, unsigned step) {
     const bool left = lane < kHaloRows;
     real qx = real(0.);
     if (left ? need_l : need_r) {
@@ -751,9 +877,10 @@ __device__ __forceinline__ real halo_chunk(const KArgs &a, const Planes &S, int 
         const int hy = min(max(yb + dir * (lane & (kHaloRows - 1)), ylo), yhi);
         real dh[18];
         Mom mh;
+        double bwh[2];
         real qy;
         row_issue<ST, BC>(a, S, hxw, hy, dh);
-        row_finish<ST, BC, F>(a, S, hxw, hxin, hy, dh, mh, qx, qy);
+        row_finish<ST, BC, F>(a, S, hxw, hxin, hy, dh, mh, bwh, qx, qy, step);
     }
     return qx;
 }
@@ -794,17 +921,18 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
 
     // halo Q_x from the gathered chunk (outer wavefronts only)
     real qh = real(0.);
-    if (edge_l || edge_r) qh = halo_chunk<ST, BC, F>(a, S, x0, lane, ys, dir, y0, y1 - 1, edge_l, edge_r);
+    if (edge_l || edge_r) qh = halo_chunk<ST, BC, F>(a, S, x0, lane, ys, dir, y0, y1 - 1, edge_l, edge_r, step);
 
     // two row states used alternately (the loop is unrolled by two); qyb is
     // Q_y of the row behind the current one
     real dA[18], dB[18];
     Mom mA, mB;
+    double bwA[2], bwB[2];  // FP64 wall values (bounded grids)
     real qyb, qxA, qyA, qxB, qyB;
     row_issue<ST, BC>(a, S, xw, ys - dir, dA);
-    row_finish<ST, BC, F>(a, S, xw, xin, ys - dir, dA, mA, qxA, qyb);
+    row_finish<ST, BC, F>(a, S, xw, xin, ys - dir, dA, mA, bwA, qxA, qyb, step);
     row_issue<ST, BC>(a, S, xw, ys, dA);
-    int kA = row_finish<ST, BC, F>(a, S, xw, xin, ys, dA, mA, qxA, qyA), kB;
+    int kA = row_finish<ST, BC, F>(a, S, xw, xin, ys, dA, mA, bwA, qxA, qyA, step), kB;
     int sc = 0;  // LDS slot of the current row
     if (LW > 1) {
         if (lane == 0) qedge[0][w][0] = qxA;
@@ -813,16 +941,16 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
 
     // One row (k rows into the march): issue the look-ahead row's loads,
     // finish it, publish its edge Q_x, then collide and store the current row.
-    auto row = [&](int k, real(&dC)[18], const Mom &mC, int kC, real qxC, real(&dN)[18], Mom &mN, int &kN,
-                   real &qxN, real &qyN) {
+    auto row = [&](int k, real(&dC)[18], const Mom &mC, const double(&bwC)[2], int kC, real qxC, real(&dN)[18],
+                   Mom &mN, double(&bwN)[2], int &kN, real &qxN, real &qyN) {
         const int y = ys + dir * k;
         row_issue<ST, BC>(a, S, xw, y + dir, dN);
         const int r = k & (kHaloRows - 1);
         if ((edge_l || edge_r) && r == 0 && k != 0)
-            qh = halo_chunk<ST, BC, F>(a, S, x0, lane, y, dir, y0, y1 - 1, edge_l, edge_r);
+            qh = halo_chunk<ST, BC, F>(a, S, x0, lane, y, dir, y0, y1 - 1, edge_l, edge_r, step);
         real qhl = readlane_real(qh, r);
         real qhr = readlane_real(qh, kHaloRows + r);
-        kN = row_finish<ST, BC, F>(a, S, xw, xin, y + dir, dN, mN, qxN, qyN);
+        kN = row_finish<ST, BC, F>(a, S, xw, xin, y + dir, dN, mN, bwN, qxN, qyN, step);
         if (LW > 1) {
             const int sn = sc == 2 ? 0 : sc + 1;
             if (lane == 0) qedge[sn][w][0] = qxN;
@@ -834,18 +962,18 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
         }
         // Q_y at y - 1 and y + 1
         const real qym = dir > 0 ? qyb : qyN, qyq = dir > 0 ? qyN : qyb;
-        collide_store<ST, BC, F>(a, D, dC, mC, kC, lane, qxC, qhl, qhr, qym, qyq, owned, vo, step);
+        collide_store<ST, BC, F>(a, D, dC, mC, bwC, kC, lane, qxC, qhl, qhr, qym, qyq, owned, vo, step);
         vo += dvo;
     };
     const int rows = y1 - y0;
     int k = 0;
     for (;;) {
         if (k >= rows) break;
-        row(k, dA, mA, kA, qxA, dB, mB, kB, qxB, qyB);
+        row(k, dA, mA, bwA, kA, qxA, dB, mB, bwB, kB, qxB, qyB);
         qyb = qyA;
         ++k;
         if (k >= rows) break;
-        row(k, dB, mB, kB, qxB, dA, mA, kA, qxA, qyA);
+        row(k, dB, mB, bwB, kB, qxB, dA, mA, bwA, kA, qxA, qyA);
         qyb = qyB;
         ++k;
     }
@@ -853,15 +981,23 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
 
 // ----------------------------------------------------------------- kernels
 // Block = kLock wavefronts on adjacent tiles of one strip (see run_strip).
+// The time step of the state read is clk[0] + sub when clk is given (the
+// launches of a captured k-step graph, whose arguments are fixed), else
+// a.step + sub.
 template <int ST, bool BC, class F>
 __global__ __launch_bounds__(kWave * kLock<ST>) void k_step(const KArgs a, const char *__restrict__ src,
-                                                            char *__restrict__ dst) {
+                                                            char *__restrict__ dst, const long long *__restrict__ clk,
+                                                            int sub) {
     constexpr int LW = kLock<ST>;
     const int blk = xcd_swizzle(blockIdx.x, gridDim.x);
     const int bxs = (a.tiles_x + LW - 1) / LW;
     const int bx = blk % bxs, sy = blk / bxs;
-    run_strip<ST, BC, F, LW>(a, src, dst, bx * LW + (int)(threadIdx.x >> 6), sy, a.step);
+    const unsigned step = (unsigned)((clk ? clk[0] : (long long)a.step) + sub);
+    run_strip<ST, BC, F, LW>(a, src, dst, bx * LW + (int)(threadIdx.x >> 6), sy, step);
 }
+
+// Sets the step clock that the launches of a captured graph read.
+__global__ void k_set_clock(long long *clk, long long n) { clk[0] = n; }
 
 // Packed step of many grids (serving).  The work list holds, first, the
 // block items of the wide grids (FP32 storage, at least kWavesPerBlock tiles
@@ -884,12 +1020,12 @@ struct WorkItem {
     int slot, tx, sy, pad_;
 };
 
-// 3 wavefronts per SIMD: with FP32 storage the two paths together would take
-// 175 VGPRs (2 per SIMD); capped at 168 the compiler keeps two values in
-// scratch.  The 16-bit codecs have the narrow path only (measured: the wide
-// one made their packed step slower).
+// 3 wavefronts per SIMD for the 16-bit codecs (168 VGPRs); 2 with FP32
+// storage, whose served grids (all bounded) form their moments in FP64 and
+// carry both the wide and the narrow path.  The 16-bit codecs have the narrow
+// path only (measured: the wide one made their packed step slower).
 template <int ST>
-__global__ __launch_bounds__(kBlock, 3) void k_step_multi(const SlotDev *__restrict__ slots,
+__global__ __launch_bounds__(kBlock, ST == LB_STORE_F32 ? 2 : 3) void k_step_multi(const SlotDev *__restrict__ slots,
                                                           const WorkItem *__restrict__ items,
                                                           const int *__restrict__ counts, int i) {
     const int nwide = counts[0], nnarrow = counts[1];
@@ -1094,7 +1230,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 struct Layout {
     int pitch;
-    size_t plane_elems, plane_bytes, pops_bytes, snap_off, snap_bytes, part_off, red_off, total;
+    size_t plane_elems, plane_bytes, pops_bytes, snap_off, snap_bytes, part_off, red_off, clk_off, total;
     int ssize;
 };
 
@@ -1109,7 +1245,8 @@ Layout layout_of(const lb_params *p) {
     L.snap_bytes = align_up((size_t)L.pitch * p->ny * sizeof(float), 256);
     L.part_off = L.snap_off + L.snap_bytes;
     L.red_off = L.part_off + align_up(kRedBlocks * kNred * sizeof(double), 256);
-    L.total = L.red_off + 256;
+    L.clk_off = L.red_off + 256;  // step clock of the captured k-step graph
+    L.total = L.clk_off + 256;
     return L;
 }
 
@@ -1196,9 +1333,22 @@ struct lb_handle {
     int bc;
     int red_blocks;
     double E0;
+    long long *clk;                  // device step clock read by the graph's launches
+    int graph_steps;                 // launches per captured graph (even), 0: host launches only
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};  // graphs starting from buffer 0 / 1
+    hipGraph_t graph[2] = {nullptr, nullptr};
 };
 
 namespace {
+
+void drop_graphs(lb_handle *h) {
+    for (int c = 0; c < 2; ++c) {
+        if (h->gexec[c]) (void)hipGraphExecDestroy(h->gexec[c]);
+        if (h->graph[c]) (void)hipGraphDestroy(h->graph[c]);
+        h->gexec[c] = nullptr;
+        h->graph[c] = nullptr;
+    }
+}
 
 void set_strip(lb_handle *h) {
     KArgs &a = h->a;
@@ -1226,6 +1376,7 @@ void set_strip(lb_handle *h) {
     }
     a.strip_rows = R;
     a.n_strips = (a.ny + R - 1) / R;
+    drop_graphs(h);
 }
 
 KArgs make_args(const lb_params *p, const Layout &L, double &E0out) {
@@ -1247,6 +1398,15 @@ KArgs make_args(const lb_params *p, const Layout &L, double &E0out) {
     a.visc = p->visc;
     a.rho_press = p->rho_extrap == LB_RHO_PRESSURE;
     a.has_force = p->g != 0.0;
+    // Dithered sums for the internal-energy form (the buoyancy-driven
+    // cavities, run for hundreds of thousands of steps towards a steady
+    // state).  Total-energy grids keep round-to-nearest: their test flows are
+    // one-dimensional by symmetry (Couette, plane acoustic waves), which exact
+    // rounding preserves column by column, and some of them (the mu ~ T
+    // Couette at Ma = 0.35, the coupled acoustic wave at Pr = 5) are unstable
+    // to transverse perturbations in the scheme itself (the FP64 reference
+    // diverges too once seeded with 1e-10 of noise).
+    a.dither = p->energy == LB_ENERGY_INTERNAL;
     const double E0 = 0.5 * p->b * p->R * p->T0;
     E0out = E0;
     a.rho0 = (real)p->rho0;
@@ -1283,22 +1443,17 @@ KArgs make_args(const lb_params *p, const Layout &L, double &E0out) {
         a.side_uy[s] = (real)p->side[s].uy;
         a.side_dth[s] = (real)(p->side[s].T / p->T0 - 1.0);
     }
+    if (p->side[0].kind == LB_BC_INLET) {
+        // Eq. 53-54: u = U0 s, rho = rho0 (1 + U0 s / c_s), T = T0 (1 + (gamma - 1) U0 s / c_s)
+        const double gamma = (p->b + 2.0) / p->b;
+        const double cs = std::sqrt(gamma * p->R * p->T0);
+        const double U0 = p->side[0].amp;
+        a.in_u = (real)U0;
+        a.in_rho = (real)(p->rho0 * U0 / cs);
+        a.in_th = (real)((gamma - 1.0) * U0 / cs);
+        a.in_rate = 1.0 / p->side[0].period;
+    }
     return a;
-}
-
-// inlet values at time step n (Eq. 53, 54), in double on the host
-void set_inlet(lb_handle *h, long n) {
-    const lb_params &p = h->p;
-    if (p.side[0].kind != LB_BC_INLET) return;
-    const double gamma = (p.b + 2.0) / p.b;
-    const double cs = std::sqrt(gamma * p.R * p.T0);
-    const double P = p.side[0].period;
-    const double ph = std::fmod((double)n, P) / P;
-    const double s = std::sin(2.0 * M_PI * ph);
-    const double U0 = p.side[0].amp;
-    h->a.in_ux = (real)(U0 * s);
-    h->a.in_drho = (real)(p.rho0 * U0 * s / cs);
-    h->a.in_dth = (real)((gamma - 1.0) * U0 * s / cs);
 }
 
 template <int ST, bool BC, class F>
@@ -1307,11 +1462,33 @@ void launch_step(lb_handle *h) {
     constexpr int LW = kLock<ST>;
     const int blocks = (a.tiles_x + LW - 1) / LW * a.n_strips;
     hipLaunchKernelGGL((k_step<ST, BC, F>), dim3(blocks), dim3(kWave * LW), 0, h->stream, a, h->pops[h->cur],
-                       h->pops[1 - h->cur]);
+                       h->pops[1 - h->cur], (const long long *)nullptr, 0);
+}
+
+// Kernel and launch shape of one step, for graph capture.
+template <int ST, bool BC, class F>
+void step_kernel(const lb_handle *h, void *&fn, int &blocks, int &threads) {
+    constexpr int LW = kLock<ST>;
+    fn = (void *)k_step<ST, BC, F>;
+    blocks = (h->a.tiles_x + LW - 1) / LW * h->a.n_strips;
+    threads = kWave * LW;
 }
 
 typedef void (*step_fn)(lb_handle *);
+typedef void (*kern_fn)(const lb_handle *, void *&, int &, int &);
 // kind: 0 periodic with runtime switches, 1 bounded, 2 periodic main configuration
+kern_fn pick_kernel(int st, int kind) {
+    static const kern_fn tbl[3][3] = {
+        {step_kernel<LB_STORE_F32, false, Dyn>, step_kernel<LB_STORE_F32, true, Dyn>,
+         step_kernel<LB_STORE_F32, false, Head>},
+        {step_kernel<LB_STORE_F16, false, Dyn>, step_kernel<LB_STORE_F16, true, Dyn>,
+         step_kernel<LB_STORE_F16, false, Head>},
+        {step_kernel<LB_STORE_BF16, false, Dyn>, step_kernel<LB_STORE_BF16, true, Dyn>,
+         step_kernel<LB_STORE_BF16, false, Head>},
+    };
+    return tbl[st][kind];
+}
+
 step_fn pick_step(int st, int kind) {
     static const step_fn tbl[3][3] = {
         {launch_step<LB_STORE_F32, false, Dyn>, launch_step<LB_STORE_F32, true, Dyn>,
@@ -1331,7 +1508,7 @@ bool is_head(const KArgs &a) {
 
 template <int ST, bool BC>
 void launch_macros(lb_handle *h, float *o0, float *o1, float *o2, float *o3, int opitch, int full) {
-    set_inlet(h, h->n);
+    h->a.step = (unsigned)h->n;
     const int n = h->a.nx * h->a.ny;
     hipLaunchKernelGGL((k_macros<ST, BC>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, h->stream, h->a,
                        h->pops[h->cur], o0, o1, o2, o3, opitch, full, (float)h->p.T0);
@@ -1339,7 +1516,7 @@ void launch_macros(lb_handle *h, float *o0, float *o1, float *o2, float *o3, int
 
 template <int ST, bool BC>
 void launch_pops(lb_handle *h, float *out, long long oplane, int q0, int nq) {
-    set_inlet(h, h->n);
+    h->a.step = (unsigned)h->n;
     const int n = h->a.nx * h->a.ny;
     hipLaunchKernelGGL((k_pops<ST, BC>), dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, h->stream, h->a,
                        h->pops[h->cur], out, oplane, q0, nq);
@@ -1347,7 +1524,7 @@ void launch_pops(lb_handle *h, float *out, long long oplane, int q0, int nq) {
 
 template <int ST, bool BC>
 void launch_diag(lb_handle *h, int use_snap, int write_snap) {
-    set_inlet(h, h->n);
+    h->a.step = (unsigned)h->n;
     hipLaunchKernelGGL((k_diag<ST, BC>), dim3(h->red_blocks), dim3(kBlock), 0, h->stream, h->a, h->pops[h->cur],
                        h->snap, use_snap, write_snap, h->partials);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, h->stream, h->partials, h->red_blocks, h->red);
@@ -1355,7 +1532,7 @@ void launch_diag(lb_handle *h, int use_snap, int write_snap) {
 
 template <int ST, bool BC>
 void launch_diag_to(lb_handle *h, int use_snap, int write_snap, double *out) {
-    set_inlet(h, h->n);
+    h->a.step = (unsigned)h->n;
     hipLaunchKernelGGL((k_diag<ST, BC>), dim3(h->red_blocks), dim3(kBlock), 0, h->stream, h->a, h->pops[h->cur],
                        h->snap, use_snap, write_snap, h->partials);
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, h->stream, h->partials, h->red_blocks, out);
@@ -1379,6 +1556,40 @@ void launch_init(lb_handle *h, const float *fields, long long fplane) {
             if (bc_) FN<LB_STORE_BF16, true>(__VA_ARGS__); else FN<LB_STORE_BF16, false>(__VA_ARGS__); \
         }                                                                                        \
     } while (0)
+
+constexpr int kGraphSteps = 32;  // default launches per captured graph
+
+// The k-step graph of a handle whose state starts in buffer c: k launches of
+// the step kernel, launch i reading buffer (c + i) & 1 at time clk + i.  k is
+// even, so a replay leaves the state in buffer c again.  The graph bakes the
+// kernel arguments in; it is dropped whenever they change (strip height).
+lb_status build_step_graph(lb_handle *h, int c, int kind) {
+    void *fn = nullptr;
+    int blocks = 0, threads = 0;
+    pick_kernel(h->p.storage, kind)(h, fn, blocks, threads);
+    HIPCHK(hipGraphCreate(&h->graph[c], 0));
+    hipGraphNode_t prev = nullptr;
+    for (int i = 0; i < h->graph_steps; ++i) {
+        KArgs a = h->a;
+        const char *src = h->pops[(c + i) & 1];
+        char *dst = h->pops[(c + i + 1) & 1];
+        const long long *clk = h->clk;
+        int sub = i;
+        void *args[5] = {(void *)&a, (void *)&src, (void *)&dst, (void *)&clk, (void *)&sub};
+        hipKernelNodeParams kp{};
+        kp.func = fn;
+        kp.gridDim = dim3(blocks);
+        kp.blockDim = dim3(threads);
+        kp.sharedMemBytes = 0;
+        kp.kernelParams = args;
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        HIPCHK(hipGraphAddKernelNode(&node, h->graph[c], prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        prev = node;
+    }
+    HIPCHK(hipGraphInstantiate(&h->gexec[c], h->graph[c], nullptr, nullptr, 0));
+    return LB_OK;
+}
 
 lb_status run_diag(lb_handle *h, int use_snap, int write_snap, double out[kNred]) {
     DISPATCH(h, launch_diag, h, use_snap, write_snap);
@@ -1418,6 +1629,8 @@ lb_status lb_create(const lb_params *p, void *dev_state, size_t bytes, void *hip
     h->snap = (float *)(h->base + L.snap_off);
     h->partials = (double *)(h->base + L.part_off);
     h->red = (double *)(h->base + L.red_off);
+    h->clk = (long long *)(h->base + L.clk_off);
+    h->graph_steps = kGraphSteps;
     h->cur = 0;
     h->n = 0;
     h->have_snap = 0;
@@ -1431,7 +1644,11 @@ lb_status lb_create(const lb_params *p, void *dev_state, size_t bytes, void *hip
     return LB_OK;
 }
 
-void lb_destroy(lb_handle *h) { delete h; }
+void lb_destroy(lb_handle *h) {
+    if (!h) return;
+    drop_graphs(h);
+    delete h;
+}
 
 const char *lb_last_error(void) { return g_err.c_str(); }
 
@@ -1481,15 +1698,40 @@ lb_status lb_init(lb_handle *h, const double *rho, const double *ux, const doubl
 lb_status lb_step(lb_handle *h, long n) {
     if (!h) return fail(LB_EINVAL, "null handle");
     if (n < 0) return fail(LB_EINVAL, "negative step count");
-    const step_fn fn = pick_step(h->p.storage, h->bc ? 1 : (is_head(h->a) ? 2 : 0));
+    const int kind = h->bc ? 1 : (is_head(h->a) ? 2 : 0);
+    // whole batches of graph_steps as replays of the captured graph, each
+    // after a one-thread launch that sets the clock its launches read
+    while (h->graph_steps > 0 && n >= h->graph_steps) {
+        const int c = h->cur;
+        if (!h->gexec[c]) {
+            const lb_status st = build_step_graph(h, c, kind);
+            if (st != LB_OK) {
+                drop_graphs(h);
+                return st;
+            }
+        }
+        hipLaunchKernelGGL(k_set_clock, dim3(1), dim3(1), 0, h->stream, h->clk, (long long)h->n);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipGraphLaunch(h->gexec[c], h->stream));
+        h->n += h->graph_steps;
+        n -= h->graph_steps;
+    }
+    const step_fn fn = pick_step(h->p.storage, kind);
     for (long s = 0; s < n; ++s) {
-        set_inlet(h, h->n);
         h->a.step = (unsigned)h->n;
         fn(h);
         h->cur ^= 1;
         h->n += 1;
     }
     HIPCHK(hipGetLastError());
+    return LB_OK;
+}
+
+lb_status lb_set_graph_steps(lb_handle *h, int k) {
+    if (!h) return fail(LB_EINVAL, "null handle");
+    if (k < 0 || k > 4096 || (k & 1)) return fail(LB_EINVAL, "graph steps: 0 or an even number <= 4096");
+    h->graph_steps = k;
+    drop_graphs(h);
     return LB_OK;
 }
 
@@ -1892,7 +2134,6 @@ lb_status lbs_submit(lbs_server *S, const lb_params *p, const double *rho, const
     lb_status st = validate(p);
     if (st != LB_OK) return st;
     if (p->storage != S->storage) return fail(LB_EINVAL, "request storage differs from the server's");
-    if (p->side[0].kind == LB_BC_INLET) return fail(LB_EINVAL, "the packed step serves grids without an inlet");
     if (max_steps < 1) return fail(LB_EINVAL, "max_steps must be >= 1");
     const Layout L = layout_of(p);
     if (L.total > S->pool_bytes - S->hdr) return fail(LB_ENOMEM, "request larger than the pool");

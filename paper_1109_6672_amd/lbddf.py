@@ -69,6 +69,7 @@ _SIGS = {
     "lb_save": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lb_load": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lb_set_strip_rows": (C.c_int, [C.c_void_p, C.c_int]),
+    "lb_set_graph_steps": (C.c_int, [C.c_void_p, C.c_int]),
     "lb_strip_rows": (C.c_int, [C.c_void_p]),
     "lb_stream": (C.c_void_p, [C.c_void_p]),
     "lb_destroy": (None, [C.c_void_p]),
@@ -260,6 +261,10 @@ class Solver:
 
     def set_strip_rows(self, rows: int):
         _check_in(self.lib, self.lib.lb_set_strip_rows(self.h, int(rows)))
+
+    def set_graph_steps(self, k: int):
+        """Launches per captured graph of step() (even, 0 = host launches)."""
+        _check_in(self.lib, self.lib.lb_set_graph_steps(self.h, int(k)))
 
     @property
     def strip_rows(self) -> int:

@@ -18,13 +18,22 @@ def _check(e, storage):
     assert e[0] < tol and e[1] < tol and e[2] < tol, (storage, e)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+_BF16_MISS = pytest.mark.xfail(raises=AssertionError, strict=True,
+                               reason="BF16 (8-bit mantissa) misses 2e-3 in u: measured 7.8e-3 on periodic noise, "
+                                      "5.9e-3 on the Couette flow")
+
+
+def _finite(e):
+    if not all(np.isfinite(e)):
+        raise RuntimeError(f"non-finite result: errors {e}")
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", pytest.param("bf16", marks=_BF16_MISS)])
 def test_periodic_noise(gpu, storage):
     p = W.periodic(150, 77, storage=storage)
     f = W.gaussian_fields(p, sigma=1e-3)
     _, _, _, _, e = run_pair(p, f, 200, "periodic noise")
-    if storage == "bf16" and max(e) > TOL[storage]:
-        pytest.xfail(f"bf16 storage misses 2e-3: errors {e}")
+    _finite(e)
     _check(e, storage)
 
 
@@ -62,12 +71,11 @@ def test_periodic_variants(gpu, variant):
     _check(e, "f32")
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "bf16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", pytest.param("bf16", marks=_BF16_MISS)])
 def test_couette(gpu, storage):
     p = W.couette(storage=storage)
     _, _, _, _, e = run_pair(p, W.rest_fields(p), 3000, "couette")
-    if storage == "bf16" and max(e) > TOL[storage]:
-        pytest.xfail(f"bf16 storage misses 2e-3: errors {e}")
+    _finite(e)
     _check(e, storage)
 
 
@@ -286,3 +294,28 @@ def test_residual_matches_the_oracle(gpu):
     rs, ro = s.residual(), o.residual()
     print(f"[case] residual gpu {rs:.6e} oracle {ro:.6e}")
     assert abs(rs - ro) < 1e-3 * ro
+
+
+@pytest.mark.parametrize("case", ["periodic", "cavity", "channel"])
+def test_graph_replays_match_host_launches_bitwise(gpu, case):
+    """lb_step replays a captured graph of 32 launches whose arguments are
+    fixed (the step index comes from a device clock, the inlet phase is
+    computed on the device from it); launched one by one from the host the
+    same 100 steps give the same populations bit for bit (3 replays plus 4
+    single launches against 100 single launches)."""
+    if case == "periodic":
+        p = W.periodic(130, 66)
+        f = W.gaussian_fields(p, sigma=1e-3)
+    elif case == "cavity":
+        p = W.cavity(70, 1e5, 1.2, 0.06, sutherland=True)
+        f = W.conduction_fields(p)
+    else:
+        p = W.channel(nx=190, ny=9, U0=0.01, period=37.5)
+        f = W.rest_fields(p)
+    a = lbddf.Solver(p).init(*f)
+    a.set_graph_steps(0)
+    a.step(100)
+    b = lbddf.Solver(p).init(*f).step(100)
+    print(f"[case] graph vs host launches, {case} {p['nx']}x{p['ny']}, 100 steps", flush=True)
+    assert a.time == b.time == 100
+    assert np.array_equal(a.populations(), b.populations())
