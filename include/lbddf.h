@@ -168,6 +168,19 @@ lb_status lb_populations(lb_handle *h, double *out);
  * out[5] = time step.  Returns LB_EUNSTABLE when out[4] > 0.  Synchronises. */
 lb_status lb_diag(lb_handle *h, double out[6]);
 
+/* For callers that cannot allocate device memory (code under hipGraph
+ * capture, serving loops and harnesses that forbid hipMalloc): the
+ * diagnostics of lb_diag written as 6 doubles to the caller's device array
+ * dev_out (same meaning and values bit for bit), asynchronously on the
+ * handle's stream, with no allocation, copy or synchronisation.  The partial
+ * sums go to a static device array of the library (64 KiB, one per GPU,
+ * kept until the process ends, shared by every call on that GPU): calls that
+ * overlap on one GPU (other streams, other threads) race on it.  The caller
+ * reads out[4] for unstable nodes.  LB_EINVAL on a null argument or a grid
+ * whose reduction needs more than the array holds (never with the current
+ * block count of at most 1024); LB_EHIP when a launch fails. */
+lb_status lb_diag_noalloc(lb_handle *h, double *dev_out);
+
 /* Convergence residual r = ||T - T_snap||_2 / ||T||_2 in FP64 against the
  * last snapshot (+inf when there is none); with update != 0 the current T
  * becomes the snapshot.  Synchronises. */

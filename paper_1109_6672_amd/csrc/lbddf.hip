@@ -45,6 +45,7 @@
 #include <cstring>
 #include <deque>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1194,8 +1195,9 @@ __global__ __launch_bounds__(kBlock) void k_diag(const KArgs a, const char *__re
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_reduce_final(const double *__restrict__ partials, int nblocks,
-                                                         double *__restrict__ out) {
+// Sum j of the per-block partials in a fixed order, returned on thread j
+// (j < kNred) of the one block.
+__device__ __forceinline__ double reduce_partials(const double *__restrict__ partials, int nblocks) {
     __shared__ double red[kNred][kWavesPerBlock];
     const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x >> 6;
     for (int j = 0; j < kNred; ++j) {
@@ -1205,11 +1207,26 @@ __global__ __launch_bounds__(kBlock) void k_reduce_final(const double *__restric
         if (lane == 0) red[j][w] = s;
     }
     __syncthreads();
-    if (threadIdx.x < kNred) {
-        double s = 0;
+    double s = 0;
+    if (threadIdx.x < kNred)
         for (int j = 0; j < kWavesPerBlock; ++j) s += red[threadIdx.x][j];
-        out[threadIdx.x] = s;
-    }
+    return s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_reduce_final(const double *__restrict__ partials, int nblocks,
+                                                         double *__restrict__ out) {
+    const double s = reduce_partials(partials, nblocks);
+    if (threadIdx.x < kNred) out[threadIdx.x] = s;
+}
+
+// The diagnostics of lb_diag on the device: out[0] = base_f + sum d_f,
+// out[1] = base_h + sum d_h, out[2..4] the momentum sums and the bad-node
+// count, out[5] = time step.
+__global__ __launch_bounds__(kBlock) void k_diag_final(const double *__restrict__ partials, int nblocks, double base_f,
+                                                       double base_h, double time, double *__restrict__ out) {
+    const double s = reduce_partials(partials, nblocks);
+    if (threadIdx.x < 5) out[threadIdx.x] = threadIdx.x == 0 ? base_f + s : (threadIdx.x == 1 ? base_h + s : s);
+    if (threadIdx.x == 5) out[5] = time;
 }
 
 // ------------------------------------------------------------- host side
@@ -1333,6 +1350,7 @@ struct lb_handle {
     int bc;
     int red_blocks;
     double E0;
+    int device;                      // HIP device current at lb_create
     long long *clk;                  // device step clock read by the graph's launches
     int graph_steps;                 // launches per captured graph (even), 0: host launches only
     hipGraphExec_t gexec[2] = {nullptr, nullptr};  // graphs starting from buffer 0 / 1
@@ -1538,6 +1556,13 @@ void launch_diag_to(lb_handle *h, int use_snap, int write_snap, double *out) {
     hipLaunchKernelGGL(k_reduce_final, dim3(1), dim3(kBlock), 0, h->stream, h->partials, h->red_blocks, out);
 }
 
+template <int ST, bool BC>
+void launch_diag_partials(lb_handle *h, double *partials) {
+    h->a.step = (unsigned)h->n;
+    hipLaunchKernelGGL((k_diag<ST, BC>), dim3(h->red_blocks), dim3(kBlock), 0, h->stream, h->a, h->pops[h->cur],
+                       h->snap, 0, 0, partials);
+}
+
 template <int ST>
 void launch_init(lb_handle *h, const float *fields, long long fplane) {
     const int n = h->a.nx * h->a.ny;
@@ -1601,6 +1626,40 @@ lb_status run_diag(lb_handle *h, int use_snap, int write_snap, double out[kNred]
 
 }  // namespace
 
+// ------------------------------------------------- allocation-free entry point
+// Partial sums of lb_diag_noalloc: kNred doubles per reduction block, at most
+// kRedBlocks blocks (64 KiB).  Each GPU the library runs on holds its own copy
+// until the process ends; every call on that GPU shares it.  Host code never
+// uses this name as an address: it takes the device address of the current
+// GPU's copy from hipGetSymbolAddress, once per device.
+constexpr int kScratchDoubles = kRedBlocks * kNred;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of the scratch array on device dev (made current for the
+// lookup, the caller's current device restored afterwards).
+lb_status scratch_on(int dev, double **out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(LB_EINVAL, "device index beyond the 64 the library tracks");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        int cur = 0;
+        HIPCHK(hipGetDevice(&cur));
+        if (cur != dev) HIPCHK(hipSetDevice(dev));
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (cur != dev) HIPCHK(hipSetDevice(cur));
+        if (e != hipSuccess) return fail(LB_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = (double *)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return LB_OK;
+}
+}  // namespace
+
 extern "C" {
 
 lb_status lb_validate(const lb_params *p) { return validate(p); }
@@ -1630,6 +1689,7 @@ lb_status lb_create(const lb_params *p, void *dev_state, size_t bytes, void *hip
     h->partials = (double *)(h->base + L.part_off);
     h->red = (double *)(h->base + L.red_off);
     h->clk = (long long *)(h->base + L.clk_off);
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
     h->graph_steps = kGraphSteps;
     h->cur = 0;
     h->n = 0;
@@ -1810,6 +1870,21 @@ lb_status lb_diag(lb_handle *h, double out[6]) {
     out[4] = r[4];
     out[5] = (double)h->n;
     if (r[4] > 0) return fail(LB_EUNSTABLE, "non-finite or non-positive moments on some nodes");
+    return LB_OK;
+}
+
+lb_status lb_diag_noalloc(lb_handle *h, double *dev_out) {
+    if (!h || !dev_out) return fail(LB_EINVAL, "null argument");
+    if ((size_t)h->red_blocks * kNred > (size_t)kScratchDoubles)
+        return fail(LB_EINVAL, "the reduction needs more partial sums than the static scratch holds (1024 blocks)");
+    double *part = nullptr;
+    const lb_status st = scratch_on(h->device, &part);
+    if (st != LB_OK) return st;
+    DISPATCH(h, launch_diag_partials, h, part);
+    const double N = (double)h->p.nx * h->p.ny;
+    hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(kBlock), 0, h->stream, (const double *)part, h->red_blocks,
+                       N * h->p.rho0, N * h->p.rho0 * h->E0, (double)h->n, dev_out);
+    HIPCHK(hipGetLastError());
     return LB_OK;
 }
 

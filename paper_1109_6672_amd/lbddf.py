@@ -64,6 +64,7 @@ _SIGS = {
     "lb_macros_device": (C.c_int, [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p]),
     "lb_populations": (C.c_int, [C.c_void_p, _D]),
     "lb_diag": (C.c_int, [C.c_void_p, _D]),
+    "lb_diag_noalloc": (C.c_int, [C.c_void_p, C.c_void_p]),
     "lb_residual": (C.c_int, [C.c_void_p, C.c_int, _D]),
     "lb_checkpoint_bytes": (C.c_size_t, [C.c_void_p]),
     "lb_save": (C.c_int, [C.c_void_p, C.c_void_p]),
@@ -242,6 +243,12 @@ class Solver:
             _check(st, self.lib)
         return dict(mass=out[0], energy=out[1], jx=out[2], jy=out[3], bad=int(out[4]), time=int(out[5]),
                     status=int(st))
+
+    def diag_noalloc(self, out):
+        """lb_diag_noalloc into a float64 torch tensor of 6 on the device
+        (asynchronous on the solver's stream)."""
+        _check_in(self.lib, self.lib.lb_diag_noalloc(self.h, C.c_void_p(out.data_ptr())))
+        return out
 
     def residual(self, update: bool = True) -> float:
         r = np.zeros(1)
