@@ -230,7 +230,9 @@ const char *lb_last_error(void);
  * each batch, so a request runs to the next multiple of k) or became unstable,
  * stores their final fields on the host, frees their memory and admits
  * waiting requests.
- * Requests of one server share its storage type.
+ * Requests of one server share its storage type; inlet sides are not served
+ * (the packed step is compiled for grids with walls, outlet or periodic
+ * sides).
  * One server must not be used by two threads at once.
  * ------------------------------------------------------------------------ */
 typedef struct lbs_server lbs_server;

@@ -46,6 +46,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <type_traits>
 #include <string>
 #include <vector>
 
@@ -110,11 +111,16 @@ struct KArgs {
 // constant tau_f) at compile time so that no dead branch is evaluated.
 struct Dyn {
     static constexpr bool fixed = false, total = false, heat = false, coupled = false, corr = false,
-                          force = false, bgk = false, ctau = false;
+                          force = false, bgk = false, ctau = false, precise = false;
+};
+// Dyn for grids with walls: FP64 moments and wall rebuild with FP32 storage
+// (see MomType)
+struct DynW : Dyn {
+    static constexpr bool precise = true;
 };
 struct Head {
     static constexpr bool fixed = true, total = true, heat = true, coupled = true, corr = true, force = false,
-                          bgk = false, ctau = true;
+                          bgk = false, ctau = true, precise = false;
 };
 #define F_TOTAL (F::fixed ? F::total : (bool)a.total)
 #define F_HEAT (F::fixed ? F::heat : (bool)a.heat)
@@ -286,7 +292,7 @@ typedef MomT<real> Mom;
 // rounding of the stored values dominates and FP32 suffices.
 template <bool P> struct MomType { typedef real type; };
 template <> struct MomType<true> { typedef double type; };
-template <int ST, bool BC> constexpr bool kPrecise = BC && ST == LB_STORE_F32;
+template <int ST, bool BC, class F> constexpr bool kPrecise = BC && F::precise && ST == LB_STORE_F32;
 
 // Pull-gather (Eq. 45): population a of node (x, y) is the post-collision
 // value stored at (x, y) - e_a, with periodic wrap.  Sources of a bounded
@@ -509,13 +515,13 @@ __device__ __forceinline__ void node_issue(const KArgs &a, const Planes &S, int 
 template <int ST, bool BC, class F>
 __device__ __forceinline__ int node_finish(const KArgs &a, const Planes &S, int x, int y, real d[18], Mom &m,
                                            double bw[2], unsigned step) {
-    typedef typename MomType<kPrecise<ST, BC>>::type T;
+    typedef typename MomType<kPrecise<ST, BC, F>>::type T;
     m = moments<F>(a, d);
     if (!BC) return K_INTERIOR;
     const BInfo b = classify(a, x, y);
     if (b.kind == K_INTERIOR || b.kind == K_OUTLET) return b.kind;  // outlet: exact copy of the neighbour
     MomT<T> mb;
-    if (b.kind == K_INLET) {
+    if (!F::precise && b.kind == K_INLET) {  // a grid with walls has no inlet
         // s = sin(2 pi n / P) at the time n of the state (Eq. 53): the phase
         // n / P reduced in FP64, the sine in the arithmetic type
         const double t = (double)step * a.in_rate;
@@ -627,9 +633,11 @@ __device__ __forceinline__ void collide(const KArgs &a, const real d[18], const 
         mt.jy = mt.rho * mt.uy;
     }
     if (!PR) mt = mom_cast<T>(m);
+    // FP32 equilibria: the h update of the FP32 path and the inlet (a grid
+    // with walls has no inlet, and its h update runs in the moment type)
     real fe[9], he[9];
-    equilibria<F>(a, m, fe, he);
-    if (kind == K_INLET) {
+    if (!PR) equilibria<F>(a, m, fe, he);
+    if (!PR && kind == K_INLET) {
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
             o[q] = fe[q];
@@ -722,15 +730,6 @@ __device__ __forceinline__ void collide(const KArgs &a, const real d[18], const 
         o[7] = (PR && a.dither) ? add_dithered(d[7], (a2 - X2 - Y2 + Pxy), plane_bits(rb, 7)) : d[7] + (a2 - X2 - Y2 + Pxy);
         o[8] = (PR && a.dither) ? add_dithered(d[8], (a2 + X2 - Y2 - Pxy), plane_bits(rb, 8)) : d[8] + (a2 + X2 - Y2 - Pxy);
     }
-    // The zeroth moment of h_eq must equal the energy of the node, i.e. the raw
-    // sum of its h, so that the BGK relaxation of h conserves energy.  The
-    // weights 4/9, 1/9, 1/36 are not representable in binary and round with
-    // one common relative error (about +7e-9 in FP32): the plain sum would
-    // add that fraction of the local energy deviation every step, a steady
-    // heat source that follows the gravity stratification and biases the
-    // flow.  h_eq of the rest velocity absorbs the remainder.
-    he[0] = (((d[9] + d[10]) + (d[11] + d[12])) + ((d[13] + d[14]) + (d[15] + d[16])) + d[17]) -
-            (((he[1] + he[2]) + (he[3] + he[4])) + ((he[5] + he[6]) + (he[7] + he[8])));
     // h: BGK plus the coupling term (1 - omega_h/2)(Z/tau_hf)(f - f_eq + C/2), Z = e.u
     if (PR) {
         // in the moment type: the equilibria and the non-equilibrium h - h_eq
@@ -753,6 +752,15 @@ __device__ __forceinline__ void collide(const KArgs &a, const real d[18], const 
         }
         return;
     }
+    // The zeroth moment of h_eq must equal the energy of the node, i.e. the raw
+    // sum of its h, so that the BGK relaxation of h conserves energy.  The
+    // weights 4/9, 1/9, 1/36 are not representable in binary and round with
+    // one common relative error (about +7e-9 in FP32): the plain sum would
+    // add that fraction of the local energy deviation every step, a steady
+    // heat source that follows the gravity stratification and biases the
+    // flow.  h_eq of the rest velocity absorbs the remainder.
+    he[0] = (((d[9] + d[10]) + (d[11] + d[12])) + ((d[13] + d[14]) + (d[15] + d[16])) + d[17]) -
+            (((he[1] + he[2]) + (he[3] + he[4])) + ((he[5] + he[6]) + (he[7] + he[8])));
     const real wh = t.omega_h;
 #pragma unroll
     for (int q = 0; q < 9; ++q) o[9 + q] = d[9 + q] - wh * (d[9 + q] - he[q]);
@@ -802,6 +810,7 @@ template <int ST, bool BC>
 __device__ __forceinline__ void row_issue(const KArgs &a, const Planes &S, int xw, int y, real d[18]) {
     bool yin;
     const int yw = row_wrap(a, y, yin);
+    if (BC && !yin) return;  // outside a bounded axis: only its Q (zero) is used
     node_issue<ST, BC>(a, S, xw, yw, d);
 }
 
@@ -811,6 +820,12 @@ __device__ __forceinline__ int row_finish(const KArgs &a, const Planes &S, int x
                                           Mom &m, double bw[2], real &Qx, real &Qy, unsigned step) {
     bool yin;
     const int yw = row_wrap(a, y, yin);
+    if (BC && !yin) {
+        // a row outside a bounded axis feeds only Q_y to the boundary row
+        // next to it, whose correction term is zero
+        Qx = Qy = real(0.);
+        return K_INTERIOR;
+    }
     const int kind = node_finish<ST, BC, F>(a, S, xw, yw, d, m, bw, step);
     const real mq = (F_CORR && xin && yin) ? -m.rho * m.dth : real(0.);
     Qx = mq * m.ux;
@@ -839,10 +854,10 @@ __device__ __forceinline__ void collide_store(const KArgs &a, const Planes &D, c
 #ifdef LB_ARITH_FP64
     constexpr bool need_bits = true;
 #else
-    constexpr bool need_bits = ST != LB_STORE_F32 || kPrecise<ST, BC>;
+    constexpr bool need_bits = ST != LB_STORE_F32 || kPrecise<ST, BC, F>;
 #endif
     const unsigned h = need_bits ? hash32((vo / Codec<ST>::bytes) ^ (step * 0x9E3779B9u)) : 0u;
-    collide<F, kPrecise<ST, BC>>(a, d, m, kind, bw, phix, phiy, o, h);
+    collide<F, kPrecise<ST, BC, F>>(a, d, m, kind, bw, phix, phiy, o, h);
     if (owned) {
 #pragma unroll
         for (int q = 0; q < 18; ++q) Codec<ST>::st(D, vo, o[q], q, plane_bits(h, q));
@@ -920,9 +935,11 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
     const unsigned dvo = (unsigned)(dir * a.rs) * eb;  // store offset step (wraps for dir < 0)
     unsigned vo = ((unsigned)ys * a.rs + xw) * eb;
 
-    // halo Q_x from the gathered chunk (outer wavefronts only)
+    // halo Q_x from the gathered chunk (outer wavefronts only; a column
+    // outside a bounded axis has Q = 0 and is not gathered)
+    const bool need_l = edge_l && (a.per_x || x0 > 0), need_r = edge_r && (a.per_x || x0 + kTile < a.nx);
     real qh = real(0.);
-    if (edge_l || edge_r) qh = halo_chunk<ST, BC, F>(a, S, x0, lane, ys, dir, y0, y1 - 1, edge_l, edge_r, step);
+    if (need_l || need_r) qh = halo_chunk<ST, BC, F>(a, S, x0, lane, ys, dir, y0, y1 - 1, need_l, need_r, step);
 
     // two row states used alternately (the loop is unrolled by two); qyb is
     // Q_y of the row behind the current one
@@ -947,8 +964,8 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
         const int y = ys + dir * k;
         row_issue<ST, BC>(a, S, xw, y + dir, dN);
         const int r = k & (kHaloRows - 1);
-        if ((edge_l || edge_r) && r == 0 && k != 0)
-            qh = halo_chunk<ST, BC, F>(a, S, x0, lane, y, dir, y0, y1 - 1, edge_l, edge_r, step);
+        if ((need_l || need_r) && r == 0 && k != 0)
+            qh = halo_chunk<ST, BC, F>(a, S, x0, lane, y, dir, y0, y1 - 1, need_l, need_r, step);
         real qhl = readlane_real(qh, r);
         real qhr = readlane_real(qh, kHaloRows + r);
         kN = row_finish<ST, BC, F>(a, S, xw, xin, y + dir, dN, mN, bwN, qxN, qyN, step);
@@ -1045,7 +1062,7 @@ __global__ __launch_bounds__(kBlock, ST == LB_STORE_F32 ? 2 : 3) void k_step_mul
             const WorkItem it = items[b];
             const SlotDev &sd = slots[it.slot];
             const int c = (sd.cur + i) & 1;
-            run_strip<ST, true, Dyn, kWavesPerBlock>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]),
+            run_strip<ST, true, DynW, kWavesPerBlock>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]),
                                                      it.tx + wv, it.sy, (unsigned)(sd.n + i));
             __syncthreads();  // the next item rewrites the LDS edge slots
         } else {
@@ -1057,7 +1074,7 @@ __global__ __launch_bounds__(kBlock, ST == LB_STORE_F32 ? 2 : 3) void k_step_mul
                 const WorkItem it = items[w];
                 const SlotDev &sd = slots[it.slot];
                 const int c = (sd.cur + i) & 1;
-                run_strip<ST, true, Dyn, 1>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]), it.tx, it.sy,
+                run_strip<ST, true, DynW, 1>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]), it.tx, it.sy,
                                             (unsigned)(sd.n + i));
             }
         }
@@ -1348,6 +1365,7 @@ struct lb_handle {
     hipStream_t stream;
     int strip_user;
     int bc;
+    int walls;  // a side with a wall (Dirichlet or adiabatic)
     int red_blocks;
     double E0;
     int device;                      // HIP device current at lb_create
@@ -1494,27 +1512,28 @@ void step_kernel(const lb_handle *h, void *&fn, int &blocks, int &threads) {
 
 typedef void (*step_fn)(lb_handle *);
 typedef void (*kern_fn)(const lb_handle *, void *&, int &, int &);
-// kind: 0 periodic with runtime switches, 1 bounded, 2 periodic main configuration
+// kind: 0 periodic with runtime switches, 1 bounded without walls (inlet,
+// outlet), 2 periodic main configuration, 3 bounded with walls
 kern_fn pick_kernel(int st, int kind) {
-    static const kern_fn tbl[3][3] = {
+    static const kern_fn tbl[3][4] = {
         {step_kernel<LB_STORE_F32, false, Dyn>, step_kernel<LB_STORE_F32, true, Dyn>,
-         step_kernel<LB_STORE_F32, false, Head>},
+         step_kernel<LB_STORE_F32, false, Head>, step_kernel<LB_STORE_F32, true, DynW>},
         {step_kernel<LB_STORE_F16, false, Dyn>, step_kernel<LB_STORE_F16, true, Dyn>,
-         step_kernel<LB_STORE_F16, false, Head>},
+         step_kernel<LB_STORE_F16, false, Head>, step_kernel<LB_STORE_F16, true, DynW>},
         {step_kernel<LB_STORE_BF16, false, Dyn>, step_kernel<LB_STORE_BF16, true, Dyn>,
-         step_kernel<LB_STORE_BF16, false, Head>},
+         step_kernel<LB_STORE_BF16, false, Head>, step_kernel<LB_STORE_BF16, true, DynW>},
     };
     return tbl[st][kind];
 }
 
 step_fn pick_step(int st, int kind) {
-    static const step_fn tbl[3][3] = {
+    static const step_fn tbl[3][4] = {
         {launch_step<LB_STORE_F32, false, Dyn>, launch_step<LB_STORE_F32, true, Dyn>,
-         launch_step<LB_STORE_F32, false, Head>},
+         launch_step<LB_STORE_F32, false, Head>, launch_step<LB_STORE_F32, true, DynW>},
         {launch_step<LB_STORE_F16, false, Dyn>, launch_step<LB_STORE_F16, true, Dyn>,
-         launch_step<LB_STORE_F16, false, Head>},
+         launch_step<LB_STORE_F16, false, Head>, launch_step<LB_STORE_F16, true, DynW>},
         {launch_step<LB_STORE_BF16, false, Dyn>, launch_step<LB_STORE_BF16, true, Dyn>,
-         launch_step<LB_STORE_BF16, false, Head>},
+         launch_step<LB_STORE_BF16, false, Head>, launch_step<LB_STORE_BF16, true, DynW>},
     };
     return tbl[st][kind];
 }
@@ -1697,6 +1716,9 @@ lb_status lb_create(const lb_params *p, void *dev_state, size_t bytes, void *hip
     h->stream = (hipStream_t)hip_stream;
     h->strip_user = 0;
     h->bc = !(h->a.per_x && h->a.per_y);
+    h->walls = 0;
+    for (int sd = 0; sd < 4; ++sd)
+        if (p->side[sd].kind == LB_BC_WALL || p->side[sd].kind == LB_BC_ADIABATIC) h->walls = 1;
     const long long nodes = (long long)p->nx * p->ny;
     h->red_blocks = (int)std::min<long long>(kRedBlocks, (nodes + kBlock - 1) / kBlock);
     set_strip(h);
@@ -1758,7 +1780,7 @@ lb_status lb_init(lb_handle *h, const double *rho, const double *ux, const doubl
 lb_status lb_step(lb_handle *h, long n) {
     if (!h) return fail(LB_EINVAL, "null handle");
     if (n < 0) return fail(LB_EINVAL, "negative step count");
-    const int kind = h->bc ? 1 : (is_head(h->a) ? 2 : 0);
+    const int kind = h->bc ? (h->walls ? 3 : 1) : (is_head(h->a) ? 2 : 0);
     // whole batches of graph_steps as replays of the captured graph, each
     // after a one-thread launch that sets the clock its launches read
     while (h->graph_steps > 0 && n >= h->graph_steps) {
@@ -2209,6 +2231,8 @@ lb_status lbs_submit(lbs_server *S, const lb_params *p, const double *rho, const
     lb_status st = validate(p);
     if (st != LB_OK) return st;
     if (p->storage != S->storage) return fail(LB_EINVAL, "request storage differs from the server's");
+    if (p->side[0].kind == LB_BC_INLET)
+        return fail(LB_EINVAL, "the packed step serves grids without an inlet (walls, outlet or periodic sides)");
     if (max_steps < 1) return fail(LB_EINVAL, "max_steps must be >= 1");
     const Layout L = layout_of(p);
     if (L.total > S->pool_bytes - S->hdr) return fail(LB_ENOMEM, "request larger than the pool");
