@@ -79,11 +79,12 @@ def test_couette(gpu, storage):
     _check(e, storage)
 
 
-def test_couette_full_length(gpu):
-    """The Couette workload at its full length (20,000 steps), FP32 storage."""
-    p = W.couette()
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_couette_full_length(gpu, storage):
+    """The Couette workload at its full length (20,000 steps)."""
+    p = W.couette(storage=storage)
     _, _, _, _, e = run_pair(p, W.rest_fields(p), 20000, "couette 20k")
-    _check(e, "f32")
+    _check(e, storage)
 
 
 def test_paper_couette_power_law_adiabatic(gpu):

@@ -324,3 +324,46 @@ def test_large_dT_cavity_512_heat_balance():
         assert d["bad"] == 0
         assert cold.mean() > hot.mean()
         s.close()
+
+
+def _sampled(name):
+    z = np.load(os.path.join(HERE, "golden", name))
+    sx, ox = int(z["stride"]), int(z["offset"])
+    sy, oy = int(z["stride_y"]), int(z["offset_y"])
+    return z, (slice(oy, None, sy), slice(ox, None, sx)), int(z["time"])
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("n,name", [(1024, "periodic_1024_sample.npz"), (4096, "periodic_4096_sample.npz")])
+def test_bandwidth_sweep_grids_against_the_oracle(n, name, storage):
+    """Config 4a at its sizes: periodic 1024 x 1024 for its full 1000 steps
+    and 4096 x 4096 for 10 steps (Gaussian sigma = 1e-3 on rho, u, T),
+    against the FP64 oracle on every 16th (1024^2) or 64th (4096^2) node
+    (fixtures written by tests/reference_runs.py from oracle-only runs), in
+    the launch configuration bench.py times."""
+    z, sl, steps = _sampled(name)
+    p = W.periodic(n, storage=storage)
+    print(f"[case] periodic {n}x{n} {storage}, {steps} steps, sampled oracle", flush=True)
+    s = lbddf.Solver(p).init(*W.gaussian_fields(p, sigma=1e-3)).step(steps)
+    g = tuple(a[sl] for a in s.macros())
+    e = rel_errors(g, (z["rho"], z["ux"], z["uy"], z["T"]))
+    print(f"       rel err rho {e[0]:.3e} u {e[1]:.3e} T {e[2]:.3e} (strip rows {s.strip_rows})", flush=True)
+    assert s.diag()["bad"] == 0
+    assert max(e) < TOL[storage], e
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_channel_first_5000_steps_against_the_oracle(storage):
+    """Config 4b at full size: the 2048 x 256 acoustic channel (source at
+    x = 0, amplitude 0.01, period 200 steps, Eq. 53-54; outlet at x = nx - 1)
+    after its first 5000 steps, against the FP64 oracle on every 8th node in
+    x and 64th in y (the wave is plane: all rows agree)."""
+    z, sl, steps = _sampled("channel_5000_sample.npz")
+    p = W.channel(storage=storage)
+    print(f"[case] channel 2048x256 {storage}, {steps} steps, sampled oracle", flush=True)
+    s = lbddf.Solver(p).init(*W.rest_fields(p)).step(steps)
+    g = tuple(a[sl] for a in s.macros())
+    e = rel_errors(g, (z["rho"], z["ux"], z["uy"], z["T"]))
+    print(f"       rel err rho {e[0]:.3e} u {e[1]:.3e} T {e[2]:.3e}", flush=True)
+    assert s.diag()["bad"] == 0
+    assert max(e) < TOL[storage], e
