@@ -130,7 +130,7 @@ def cpu_baseline(seconds: float):
                 cpu=cpu)
 
 
-def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 200, tol: float = 1e-8,
+def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 1000, tol: float = 1e-8,
                     cap: int = 100_000, modes=("packed", "f16", "seq"), progress: float = 0.0):
     """The continuous-batching server against one solve per launch, on the
     same seeded stream of cavity requests (Poisson arrivals, 50 per second).
@@ -138,11 +138,13 @@ def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 2
     solve per launch, FP32)."""
     from paper_1109_6672_amd import lbddf, serving as SV, workloads as W
 
-    keep = ("p50_s", "p99_s", "solves_per_s", "mlups", "wall_s", "states")
+    keep = ("p50_s", "p99_s", "converged_p50_s", "converged_p99_s", "solves_per_s", "mlups", "wall_s", "states",
+            "median_steps", "states_by_edge")
     out = {
         "workload": f"{n_requests} differentially heated cavity requests, edges {'/'.join(map(str, sizes))}, "
                     "Poisson arrivals 50/s, Ra log-uniform 1e3..1e6, dT/T0 uniform 0.02..1.2, FP32, "
-                    f"residual checked every {k_steps} steps, tol {tol:g}, plateau test, cap {cap} steps",
+                    f"residual = relative change of T over {k_steps} steps, tol {tol:g}, plateau test, "
+                    f"cap {cap} steps; one at a time = lb_step (graph replays) and one residual per check",
     }
     reqs = W.serving_mix(n_requests, sizes=sizes, rate=50.0)
     if "packed" in modes:
@@ -217,13 +219,15 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the 16-bit and smaller-grid runs")
     ap.add_argument("--no-serving", action="store_true", help="skip the packed-server comparison")
-    ap.add_argument("--serving-requests", type=int, default=24, help="requests in the serving mix")
-    ap.add_argument("--serving-sizes", default="64,128,256", help="grid edges of the serving mix")
+    ap.add_argument("--serving-requests", type=int, default=16, help="requests in the serving mix")
+    ap.add_argument("--serving-sizes", default="64,128", help="grid edges of the serving mix")
     ap.add_argument("--serving-only", action="store_true",
                     help="only the serving comparison, with progress lines on stderr")
     ap.add_argument("--serving-modes", default="packed,f16,seq",
                     help="runs of the serving comparison: packed, f16, seq (one solve per launch)")
-    ap.add_argument("--serving-cap", type=int, default=100_000, help="step cap per request")
+    ap.add_argument("--serving-cap", type=int, default=400_000, help="step cap per request")
+    ap.add_argument("--serving-k", type=int, default=1000,
+                    help="steps per batch and between residual checks (the residual is the change over them)")
     ap.add_argument("--only", default="", help="storage of a single run (profiling): f32 | f16 | bf16")
     ap.add_argument("--copy-only", action="store_true",
                     help="HBM counter calibration: 5 plain device copies of 2 GiB (torch copy kernel)")
@@ -261,6 +265,7 @@ def main():
     if args.serving_only:
         print(json.dumps(serving_compare(args.serving_requests,
                                          tuple(int(v) for v in args.serving_sizes.split(",")),
+                                         k_steps=args.serving_k,
                                          cap=args.serving_cap, modes=tuple(args.serving_modes.split(",")),
                                          progress=20.0)), flush=True)
         return

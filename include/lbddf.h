@@ -224,7 +224,7 @@ const char *lb_last_error(void);
  * per-node step as lb_step), then reads every grid's FP64 convergence
  * residual r = ||T - T_snap|| / ||T|| (snapshot k steps earlier; the first
  * at admission) in one copy,
- * retires grids that converged (r < tol), reached a plateau (r below 1e-3 of
+ * retires grids that converged (r < tol), reached a plateau (r below 1e-2 of
  * its largest value and no new minimum for max(10, n/2) of its n checks so
  * far, minima counted from that maximum), reached max_steps (checked after
  * each batch, so a request runs to the next multiple of k) or became unstable,

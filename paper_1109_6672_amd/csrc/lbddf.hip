@@ -1987,7 +1987,7 @@ double now_s() {
 }
 
 // Plateau test of the convergence residual, applied once per check: the
-// residual lies below 1e-3 of its largest value so far and has made no new
+// residual lies below 1e-2 of its largest value so far and has made no new
 // minimum for max(10, checks / 2) checks, minima being counted from that
 // maximum.  The flow's onset from a quiescent start makes the residual grow
 // first, and the humps of a decaying transient stay well above its floor;
@@ -2000,7 +2000,7 @@ bool plateau_update(double r, double &peak, double &best, int &stall, int &check
     } else if (r < best) {
         best = r;
         stall = 0;
-    } else if (++stall >= std::max(10, checks / 2) && r < 1e-3 * peak) {
+    } else if (++stall >= std::max(10, checks / 2) && r < 1e-2 * peak) {
         return true;
     }
     return false;

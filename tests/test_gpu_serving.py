@@ -128,3 +128,54 @@ def test_convergence_and_release(gpu):
     srv.release(rid)
     with pytest.raises(lbddf.LBError):
         srv.poll(rid)
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16"])
+def test_a_late_arrival_is_identical_to_alone(gpu, storage):
+    """A request that arrives while others are on the GPU and waits for a
+    retirement before it is admitted (the pool holds the two running grids
+    and not a third) gives the same fields bit for bit as when it runs alone."""
+    reqs = _requests()
+    target, others = reqs[2], [reqs[4], reqs[1]]
+    alone = lbddf.Server(_pool([target]), storage=storage, k_steps=50)
+    a = alone.submit(target[0], _fields(*target), tol=0.0, max_steps=400)
+    _run_to_end(alone)
+    room = sum(lbddf.state_bytes(dict(p, storage=storage)) + 256 for p, _ in others)
+    srv = lbddf.Server(lbddf.load().lbs_pool_overhead() + room, storage=storage, k_steps=50)
+    first = [srv.submit(p, _fields(p, k), tol=0.0, max_steps=m) for (p, k), m in zip(others, (150, 300))]
+    for _ in range(2):
+        srv.advance()
+    t = srv.submit(target[0], _fields(*target), tol=0.0, max_steps=400)
+    resident, queued = srv.advance()  # counts at the start of the batch: the target waits through it
+    assert resident == 2 and queued == 1
+    _run_to_end(srv)
+    st, big = srv.poll(t), srv.poll(first[0])
+    print(f"[case] late arrival ({storage}): submitted {st['t_submit']:.4f} s, admitted {st['t_admit']:.4f} s "
+          f"after the 260^2 grid finished at {big['t_done']:.4f} s", flush=True)
+    assert st["t_admit"] >= big["t_done"] > st["t_submit"]
+    assert st["state"] == "step_cap" and st["steps"] == 400
+    for x, y in zip(alone.result(a), srv.result(t)):
+        np.testing.assert_array_equal(x, y)
+
+
+def test_served_f16_results_against_the_oracle(gpu):
+    """Requests served with FP16 storage against the FP64 oracle, on flows
+    within the 16-bit bar: periodic noise (200 steps), the Couette flow (3000
+    steps) and a moderate-dT Sutherland cavity (600 steps).  (On the
+    gravity-driven cavities FP16 storage misses 2e-3 in u, 1.7e-3 to 7e-3,
+    served or not: the uniform rest-state shift leaves the hydrostatic and
+    thermal density contrast in the stored values.)"""
+    cases = [(W.periodic(150, 77), W.gaussian_fields(W.periodic(150, 77), sigma=1e-3), 200),
+             (W.couette(), W.rest_fields(W.couette()), 3000),
+             (W.cavity(64, 1e5, 0.6, 0.05, sutherland=True), W.conduction_fields(W.cavity(64, 1e5, 0.6, 0.05,
+                                                                                        sutherland=True)), 600)]
+    pool = lbddf.load().lbs_pool_overhead() + sum(lbddf.state_bytes(dict(p, storage="f16")) + 256 for p, _, _ in cases)
+    srv = lbddf.Server(pool, storage="f16", k_steps=100)
+    ids = [srv.submit(p, f, tol=0.0, max_steps=n) for p, f, n in cases]
+    _run_to_end(srv)
+    for rid, (p, f, n) in zip(ids, cases):
+        assert srv.poll(rid)["steps"] == n
+        ref = O.Oracle(p).init(*f).step(n).macros()
+        e = rel_errors(srv.result(rid), ref)
+        print(f"[case] served FP16 {p['nx']}x{p['ny']} after {n} steps against the oracle: {e}", flush=True)
+        assert all(np.isfinite(e)) and max(e) < TOL["f16"], e

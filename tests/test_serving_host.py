@@ -46,3 +46,12 @@ def test_minimum_is_counted_from_the_last_maximum():
     # residual would be taken for a stall after 10 checks
     seq = [1e-12] + list(np.linspace(1e-8, 1e-4, 40)) + list(1e-4 * np.exp(-0.2 * np.arange(60)))
     assert _first_plateau(seq) is None
+
+
+def test_a_floor_near_a_thousandth_of_the_peak_is_a_plateau():
+    # 16-bit storage: the residual settles near 1e-4 after an onset peak of
+    # about 0.1 and never reaches a tolerance of 1e-8
+    rng = np.random.default_rng(3)
+    seq = [0.1] + list(0.1 * np.exp(-0.15 * np.arange(1, 50))) + list(1e-4 * (1 + 0.3 * rng.random(300)))
+    i = _first_plateau(seq)
+    assert i is not None and 50 < i < 350
