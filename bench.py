@@ -16,6 +16,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -102,32 +103,68 @@ def time_gpu(n: int, storage: str, steps: int, warmup: int, strip_rows: int = 0,
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    try:
+        with open("/proc/cpuinfo") as fh:
+            return next(line.split(":", 1)[1].strip() for line in fh if line.startswith("model name"))
+    except (OSError, StopIteration):
+        return "unknown"
+
+
+def _oracle_mlups(p, fields, seconds, chunk):
+    """Oracle MLUPS on one workload: steps in chunks until `seconds` pass
+    (initialisation and a first chunk excluded)."""
+    from oracle import oracle as O
+
+    o = O.Oracle(p).init(*fields)
+    o.step(chunk)
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        o.step(chunk)
+        steps += chunk
+    t = time.perf_counter() - t0
+    o.close()
+    return p["nx"] * p["ny"] * steps / t / 1e6, steps, t
+
+
 def cpu_baseline(seconds: float):
-    """The FP64 oracle as it stands on the host cores, on a bounded sample of
-    the same workload (periodic 512 x 512, same recipe), until `seconds` pass."""
+    """The FP64 oracle as it stands on the host cores: the headline recipe on
+    a bounded sample (periodic 512 x 512) with all cores and with one thread,
+    then short samples of the Couette, small-dT cavity, large-dT 64^2 cavity
+    and acoustic-channel workloads (the oracle runs grids below 8192 nodes on
+    one thread)."""
     from oracle import oracle as O
     from paper_1109_6672_amd import workloads as W
 
-    n = 512
-    p = W.periodic(n)
-    o = O.Oracle(p).init(*W.gaussian_fields(p, sigma=1e-3))
-    o.step(1)
-    steps = 0
-    t0 = time.perf_counter()
-    while time.perf_counter() - t0 < seconds:
-        o.step(2)
-        steps += 2
-    t = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    cpu = "unknown"
-    try:
-        with open("/proc/cpuinfo") as fh:
-            cpu = next(line.split(":", 1)[1].strip() for line in fh if line.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
-    return dict(value=n * n * steps / t / 1e6, unit="MLUPS", cores=cores, kind="oracle",
-                sample=f"periodic {n}x{n}, same recipe, {steps} steps in {t:.1f} s (FP64, OpenMP over rows)",
-                cpu=cpu)
+    O.set_threads(os.cpu_count() or 1)
+    cores = O.threads()
+    p = W.periodic(512)
+    f = W.gaussian_fields(p, sigma=1e-3)
+    all_cores, steps, t = _oracle_mlups(p, f, 0.4 * seconds, 2)
+    O.set_threads(1)
+    one, steps1, t1 = _oracle_mlups(p, f, 0.2 * seconds, 1)
+    samples = [dict(workload="periodic 512x512, headline recipe", threads=cores, mlups=all_cores),
+               dict(workload="periodic 512x512, headline recipe", threads=1, mlups=one)]
+    O.set_threads(cores)
+    extra = [("Couette 4x64 (config 1)", W.couette(), W.rest_fields, 2000),
+             ("small-dT cavity 128x128 (config 2)", W.cavity(128, 1e4, 0.02, 0.02), W.noisy_temperature_fields, 20),
+             ("large-dT cavity 64x64 (config 3 downscale)", W.cavity(64, 1e5, 1.2, 0.06, sutherland=True),
+              W.conduction_fields, 50),
+             ("acoustic channel 2048x256 (config 4b)", W.channel(), W.rest_fields, 2)]
+    for name, q, make, chunk in extra:
+        m, _, _ = _oracle_mlups(q, make(q), 0.1 * seconds, chunk)
+        samples.append(dict(workload=name, threads=cores if q["nx"] * q["ny"] >= 8192 else 1, mlups=m))
+    return dict(value=all_cores, unit="MLUPS", cores=cores, kind="oracle",
+                sample=f"periodic 512x512, same recipe as the headline, {steps} steps in {t:.1f} s on {cores} "
+                       f"threads (FP64, OpenMP over rows); single thread {one:.2f} MLUPS ({steps1} steps in "
+                       f"{t1:.1f} s)", single_thread=one, samples=samples, cpu=_cpu_model())
 
 
 def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 1000, tol: float = 1e-8,

@@ -63,6 +63,9 @@
  *   - initial populations are the equilibria of the initial fields.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -708,6 +711,24 @@ double orc_residual(orc_grid *g, int update) {
         g->have_snap = 1;
     }
     return r;
+}
+
+/* Threads of the OpenMP passes (timing of the CPU baseline); ignored without
+ * OpenMP. */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+int orc_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
 }
 
 /* ---- single-node entry points used by the pins ------------------------- */

@@ -86,6 +86,8 @@ def _load():
         lib.orc_node_moments.argtypes = [C.c_void_p, _D, _D]
         lib.orc_node_collide.argtypes = [C.c_void_p, _D, C.c_double, C.c_double, _D]
         lib.orc_node_transport.argtypes = [C.c_void_p, C.c_double, C.c_double, _D]
+        lib.orc_set_threads.argtypes = [C.c_int]
+        lib.orc_threads.restype = C.c_int
         _lib = lib
     return _lib
 
@@ -237,6 +239,15 @@ class Oracle:
         o = np.empty(12)
         self.lib.orc_node_transport(self.h, rho, T, _ptr(o))
         return dict(tau_f=o[0], s=o[1:10].copy(), omega_h=o[10], inv_tau_hf=o[11])
+
+
+def set_threads(n: int):
+    """Threads of the oracle's OpenMP passes from now on (the CPU baseline)."""
+    _load().orc_set_threads(int(n))
+
+
+def threads() -> int:
+    return int(_load().orc_threads())
 
 
 def correction(phix, phiy):

@@ -773,10 +773,13 @@ __device__ __forceinline__ void collide(const KArgs &a, const real d[18], const 
     }
 }
 
-// Counter-based random bits for the stochastic rounding of the 16-bit codecs:
-// a 32-bit integer hash (two multiply-xorshift rounds) of the node's linear
+// Counter-based random bits for the stochastic rounding of the 16-bit codecs
+// and the dithered FP32 sums: a 32-bit integer hash of the node's linear
 // index and the time step, rotated by a different amount for each of the 18
-// planes so that each plane's rounding reads a different window of it.
+// planes so that each plane's rounding reads a different window of it.  The
+// hash is "lowbias32" (two multiply-xorshift rounds, multipliers 0x7feb352d
+// and 0x846ca68b), found by C. Wellons' hash-prospector search and published
+// with it.
 __device__ __forceinline__ unsigned hash32(unsigned x) {
     x ^= x >> 16;
     x *= 0x7feb352du;
