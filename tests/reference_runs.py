@@ -9,7 +9,13 @@ validation of the GPU path.  Cases (`--case`):
                  Gaussian perturbations (sigma 1e-3), 1000 steps;
   periodic_4096  the same on 4096 x 4096, 10 steps;
   channel        the acoustic channel 2048 x 256 (source at x = 0, amplitude
-                 0.01, period 200 steps, Eq. 53-54), its first 5000 steps.
+                 0.01, period 200 steps, Eq. 53-54), its first 5000 steps;
+  large_dt_sweep_1e3 / _1e4 / _1e5
+                 the paper's large-dT runs (Sec. IV-C): walls at T0 (1 +/- 0.6),
+                 Sutherland viscosity, tau_e = tau_zeta = tau_f, Ra = 1e3, 1e4,
+                 1e5 on 100, 150, 200 cells (101, 151, 201 nodes) with
+                 mu_r = 0.1, 0.1, 0.06, conduction start; 100,000, 200,000 and
+                 300,000 steps.
 
 Runs only the FP64 oracle and writes its macroscopic fields (rho, ux, uy, T)
 with the step count to an .npz file; checkpoints every `--every` steps so
@@ -63,8 +69,16 @@ def channel():
     return p, W.rest_fields(p)
 
 
+def large_dt_sweep(n, Ra, mu_r):
+    p = W.cavity(n, Ra, 1.2, mu_r, sutherland=True)
+    return p, W.conduction_fields(p)
+
+
 CASES = {"large_dt_512": (large_dt_512, 200_000), "periodic_1024": (periodic_1024, 1000),
-         "periodic_4096": (periodic_4096, 10), "channel": (channel, 5000)}
+         "periodic_4096": (periodic_4096, 10), "channel": (channel, 5000),
+         "large_dt_sweep_1e3": (lambda: large_dt_sweep(101, 1e3, 0.1), 100_000),
+         "large_dt_sweep_1e4": (lambda: large_dt_sweep(151, 1e4, 0.1), 200_000),
+         "large_dt_sweep_1e5": (lambda: large_dt_sweep(201, 1e5, 0.06), 300_000)}
 
 
 def main():

@@ -1,17 +1,20 @@
-"""The paper's acoustic set-up (Sec. IV-B): a 600-node channel driven at x = 0
-by a sound source of density amplitude 0.01 and wavelength 50 (Eq. 53-54),
-sampled at t = 800, for the Prandtl numbers (0.2, 0.5, 5 at gamma = 5/3) and
-ratios of specific heats (7/5, 9/7 at Pr = 0.5) the paper sweeps.  On the GPU
-path the coupled model's amplitude envelope follows Eq. 55-56 (fitted decay
-rate within 3 %, envelope within 7 %: Eq. 56 is the small-attenuation limit,
-and Pr = 0.2 attenuates most), the decoupled model's (theta = 1) misses it by
-more than 25 % (the claim of Fig. 5), and both runs match the FP64 oracle's
-to the FP32 bar.  Coupled at Pr = 5 the scheme carries a slowly growing mode
-(omega_h = 1.79, coupling coefficient (Pr - 1)/tau_f = 5): the GPU-oracle
-difference stays near 2e-8 in u up to t = 400 and then grows tenfold by
-t = 800 from FP32 rounding, in the bulk, not at the source; that case is held
-to 1e-4.  (Pr = 5 with gamma = 9/7 at this viscosity diverges in the oracle
-itself.)"""
+"""The paper's acoustic set-up (Sec. IV-B): a 600 x 4 channel (periodic in y)
+driven at x = 0 by a sound source of density amplitude 0.01 and wavelength
+50 (Eq. 53-54), sampled over the last period before t = 800, for the
+Prandtl numbers of Fig. 3 (0.2, 0.5, 5 at gamma = 5/3) and the ratios of
+specific heats of Fig. 4 (5/3, 7/5, 9/7 at Pr = 2), coupled and decoupled
+(theta = 1, Fig. 5).  On the GPU path the coupled model's amplitude envelope
+follows Eq. 55-56 (fitted decay rate within 3 %, envelope within 7 %: Eq. 56
+is the small-attenuation limit, and Pr = 0.2 attenuates most), the
+decoupled model's misses it by more than 25 % (the claim of Fig. 5), and
+both runs match the FP64 oracle's to the FP32 bar at t = 800.
+
+Coupled at Pr = 5 the scheme (omega_h = 1.79, coupling coefficient
+(Pr - 1)/tau_f = 5) carries a growing mode: the FP64 oracle itself
+diverges by t = 1600 from rest, and by t = 100 once seeded with 1e-10 of
+transverse noise.  The GPU fields are compared with the oracle's at
+t = 400, before that mode has grown out of the FP32 rounding; the envelope
+is still taken at t = 800."""
 import math
 
 import numpy as np
@@ -22,7 +25,7 @@ from tests.gpu_common import TOL, rel_errors
 
 pytestmark = pytest.mark.gpu
 
-NX, T_M, LAM, MU = 600, 800, 50.0, 0.1
+NX, NY, T_M, LAM, MU = 600, 4, 800, 50.0, 0.1
 
 
 def _setup(Pr, gamma, coupled):
@@ -30,7 +33,7 @@ def _setup(Pr, gamma, coupled):
     cs = math.sqrt(gamma / 3.0)
     period = LAM / cs
     U = cs * 0.01  # Eq. 54: u = c_s drho / rho0 with drho = 0.01 rho0
-    p = W.channel(nx=NX, ny=2, U0=U, period=period, tau_f=3 * MU + 0.5, Pr=Pr, b=b, correction=False,
+    p = W.channel(nx=NX, ny=NY, U0=U, period=period, tau_f=3 * MU + 0.5, Pr=Pr, b=b, correction=False,
                   coupled=coupled)
     cv, cp = b / 6.0, (b + 2.0) / 6.0
     fp = cs / LAM
@@ -49,24 +52,31 @@ def _envelope(stepper, macros, period):
     return env
 
 
-@pytest.mark.parametrize("Pr,gamma", [(0.2, 5 / 3), (0.5, 5 / 3), (5.0, 5 / 3), (0.5, 7 / 5), (0.5, 9 / 7)])
+@pytest.mark.parametrize("Pr,gamma", [(0.2, 5 / 3), (0.5, 5 / 3), (5.0, 5 / 3), (2.0, 5 / 3), (2.0, 7 / 5),
+                                      (2.0, 9 / 7)])
 @pytest.mark.parametrize("coupled", [True, False])
 def test_paper_acoustic_setup(gpu, Pr, gamma, coupled):
     from oracle import oracle as O
 
     p, cs, period, U, beta = _setup(Pr, gamma, coupled)
     s = lbddf.Solver(p).init(*W.rest_fields(p))
+    o = O.Oracle(p).init(*W.rest_fields(p))
+    t_cmp = 400 if (coupled and Pr >= 5) else T_M  # before the growing mode (see the module docstring)
+    if t_cmp < T_M:
+        s.step(t_cmp)
+        e = rel_errors(s.macros(), o.step(t_cmp).macros())
+        s.init(*W.rest_fields(p))
     env = _envelope(lambda n: s.step(n), s.macros, period)
-    o = O.Oracle(p).init(*W.rest_fields(p)).step(T_M)
-    e = rel_errors(s.macros(), o.macros())
+    if t_cmp == T_M:
+        e = rel_errors(s.macros(), o.step(T_M).macros())
     x = np.arange(NX)
     sel = (x >= 20) & (x <= min(500, int(cs * (T_M - period)) - 20))
     want = U * np.exp(-beta * x[sel])
     dev = np.abs(env[sel] / want - 1).max()
     fit = -np.polyfit(x[sel], np.log(env[sel]), 1)[0]
-    print(f"[case] acoustic Pr={Pr} gamma={gamma:.4f} coupled={coupled}: GPU vs oracle {e}, "
+    print(f"[case] acoustic Pr={Pr} gamma={gamma:.4f} coupled={coupled}: GPU vs oracle at t={t_cmp} {e}, "
           f"beta fit/Eq.56 {fit / beta:.4f}, envelope max dev {dev:.3f}", flush=True)
-    assert max(e) < (1e-4 if coupled and Pr >= 5 else TOL["f32"]), e
+    assert max(e) < TOL["f32"], e
     if coupled:
         assert abs(fit / beta - 1) < 0.03 and dev < 0.07
     else:

@@ -127,6 +127,30 @@ def test_small_dT_cavity_table_ii_other_rows(Ra, n, mu_r, cap):
         assert abs(m[k] - row[k]) < 2.0 / (n - 1) + 1e-9, (k, m[k], row[k])
 
 
+def test_table_ii_ra1e4_at_the_papers_temperatures_and_grid():
+    """Table II's Ra = 1e4 row at the paper's own conditions: walls at 315 K
+    and 285 K (dT / T0 = 0.1 about T_r = 300 K) on 150 cells (151 x 151
+    nodes), mu_r = 0.05 (tau_f = 0.65, g H / R T0 = 0.047), run to
+    convergence.  Nu, u_max and v_max within 2 % of the 'Present' row, the
+    positions within two lattice spacings."""
+    with open(os.path.join(HERE, "golden", "table2_cavity.json")) as fh:
+        tab = json.load(fh)
+    row = dict(zip(tab["columns"], next(r for r in tab["rows"] if r[0] == 1e4)))
+    p = W.cavity(151, 1e4, 0.1, 0.05)
+    print(f"[case] Table II Ra=1e4, dT/T0=0.1, 151x151, g={p['g']:.4e}", flush=True)
+    s = lbddf.Solver(p).init(*W.noisy_temperature_fields(p))
+    state, r = _converge(s, check=1000, cap=2_000_000)
+    rho, ux, uy, T = s.macros()
+    m = P.cavity_metrics(p, ux, uy, T)
+    print(f"       {state} after {s.time} steps (r = {r:.2e}): " + ", ".join(f"{k} {v:.4f}" for k, v in m.items()),
+          flush=True)
+    assert state != "step_cap" and s.diag()["bad"] == 0
+    for k in ("Nu", "u_max", "v_max"):
+        assert abs(m[k] / row[k] - 1) < 0.02, (k, m[k], row[k])
+    for k in ("y_max", "x_max"):
+        assert abs(m[k] - row[k]) < 2.0 / 150 + 1e-9, (k, m[k], row[k])
+
+
 def test_small_dT_cavity_converged_state_against_the_oracle():
     """Config 2 run 268,000 steps (its convergence above) on the GPU and in the
     FP64 oracle: FP32 arithmetic with FP32 storage within 1e-5 in rho, u and
