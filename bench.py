@@ -94,7 +94,7 @@ def time_gpu(n: int, storage: str, steps: int, warmup: int, strip_rows: int = 0,
     ms = start.elapsed_time(stop)
     d = s.diag(check=False)
     nodes = n_nodes
-    out = dict(n=n, storage=storage, steps=steps, ms_total=ms, ms_per_step=ms / steps, wall_s=wall,
+    out = dict(n=n if case is None else f"{p['nx']}x{p['ny']}", storage=storage, steps=steps, ms_total=ms, ms_per_step=ms / steps, wall_s=wall,
                mlups=nodes * steps / (ms * 1e-3) / 1e6, strip_rows=s.strip_rows, bad_nodes=d["bad"])
     out["gbs"] = BYTES_PER_NODE[storage] * nodes / (out["ms_per_step"] * 1e-3) / 1e9
     s.close()
@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--serving-k", type=int, default=1000,
                     help="steps per batch and between residual checks (the residual is the change over them)")
     ap.add_argument("--only", default="", help="storage of a single run (profiling): f32 | f16 | bf16")
+    ap.add_argument("--workload", default="periodic",
+                    help="workload of an --only run: periodic (n x n) | cavity512 | channel2048x256")
     ap.add_argument("--copy-only", action="store_true",
                     help="HBM counter calibration: 5 plain device copies of 2 GiB (torch copy kernel)")
     ap.add_argument("--pmc-summary", metavar="DIR", default="",
@@ -308,7 +310,8 @@ def main():
         return
 
     if args.only:
-        r = time_gpu(args.n, args.only, args.steps, args.warmup)
+        case = None if args.workload == "periodic" else args.workload
+        r = time_gpu(args.n, args.only, args.steps, args.warmup, case=case)
         print(json.dumps(r), flush=True)
         return
 
