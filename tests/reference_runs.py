@@ -22,7 +22,9 @@ with the step count to an .npz file; checkpoints every `--every` steps so
 that an interrupted run resumes (cases without a time-dependent boundary).
 `--golden` also writes the fields on every `--stride`-th node in x and
 `--stride-y`-th in y (default: the same), the fixtures under tests/golden/
-that tests/test_gpu_validation.py compares the GPU runs with.  Usage:
+that tests/test_gpu_validation.py compares the GPU runs with, plus the
+temperature of the three columns next to each x-side (T_left3, T_right3)
+for the wall heat fluxes.  Usage:
 
     python -m tests.reference_runs --case large_dt_512 --out ref.npz [--steps N] [--every 10000] \
         [--golden tests/golden/large_dt_512_sample.npz --stride 8]
@@ -127,7 +129,8 @@ def write_golden(full: str, golden: str, stride: int, stride_y: int):
     off, offy = stride // 2, stride_y // 2
     sl = (slice(offy, None, stride_y), slice(off, None, stride))
     np.savez_compressed(golden, rho=z["rho"][sl], ux=z["ux"][sl], uy=z["uy"][sl], T=z["T"][sl],
-                        time=z["time"], stride=stride, offset=off, stride_y=stride_y, offset_y=offy)
+                        time=z["time"], stride=stride, offset=off, stride_y=stride_y, offset_y=offy,
+                        T_left3=z["T"][:, :3], T_right3=z["T"][:, -3:])
     print(f"wrote {golden} ({z['rho'][sl].shape} nodes every {stride} from {off} in x, every {stride_y} "
           f"from {offy} in y)", flush=True)
 

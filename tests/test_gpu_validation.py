@@ -391,3 +391,46 @@ def test_channel_first_5000_steps_against_the_oracle(storage):
     print(f"       rel err rho {e[0]:.3e} u {e[1]:.3e} T {e[2]:.3e}", flush=True)
     assert s.diag()["bad"] == 0
     assert max(e) < TOL[storage], e
+
+
+def _vortex_centre(rho, ux):
+    """Centre of the primary vortex: the extremum of the stream function
+    psi(x, y) = sum over rows below y of rho u_x (one row per lattice
+    spacing), as fractions of the cavity width from the hot wall (x) and the
+    bottom (y)."""
+    psi = np.cumsum(rho * ux, axis=0)
+    j, i = np.unravel_index(np.argmax(np.abs(psi)), psi.shape)
+    return i / (rho.shape[1] - 1), j / (rho.shape[0] - 1)
+
+
+@pytest.mark.parametrize("Ra,n,mu_r", [(1e3, 101, 0.1), (1e4, 151, 0.1), (1e5, 201, 0.06)])
+def test_large_dT_cavity_paper_sweep_against_the_oracle(Ra, n, mu_r):
+    """The paper's large-dT runs (Sec. IV-C, Eq. 57-59): walls at 960 K and
+    240 K (T0 (1 +/- 0.6)), Sutherland viscosity, tau_e = tau_zeta = tau_f at
+    every node, Ra = 1e3, 1e4, 1e5 on 100, 150, 200 cells with
+    mu_r = 0.1, 0.1, 0.06, from the conduction profile; 100,000, 200,000 and
+    300,000 steps in FP32 storage against the FP64 oracle on every 5th node
+    (tests/golden/large_dt_sweep_*.npz, written by tests/reference_runs.py
+    from oracle-only runs).  On the GPU's full fields the wall heat fluxes
+    balance (cold-wall over hot-wall mean gradient within 7 % of
+    mu(T_h) / mu(T_l) = 2.619) and, at Ra = 1e3 and 1e4, the centre of the
+    primary vortex lies right of and below the cavity centre (the asymmetry
+    of Figs. 7-8)."""
+    name = f"large_dt_sweep_{'1e%d' % round(math.log10(Ra))}.npz"
+    z, sl, steps = _sampled(name)
+    p = W.cavity(n, Ra, 1.2, mu_r, sutherland=True)
+    print(f"[case] large-dT cavity {n}x{n} Ra {Ra:g} f32, {steps} steps, sampled oracle", flush=True)
+    s = lbddf.Solver(p).init(*W.conduction_fields(p)).step(steps)
+    rho, ux, uy, T = s.macros()
+    e = rel_errors((rho[sl], ux[sl], uy[sl], T[sl]), (z["rho"], z["ux"], z["uy"], z["T"]))
+    xc, yc = _vortex_centre(rho, ux)
+    hot = np.abs(-3 * T[:, 0] + 4 * T[:, 1] - T[:, 2]).mean() / 2
+    cold = np.abs(3 * T[:, -1] - 4 * T[:, -2] + T[:, -3]).mean() / 2
+    mu_ratio = 1.6 ** 1.5 / 0.4 ** 1.5 * (0.4 + 110.5 / 600) / (1.6 + 110.5 / 600)  # Eq. 59
+    print(f"       rel err rho {e[0]:.3e} u {e[1]:.3e} T {e[2]:.3e}; vortex centre ({xc:.3f}, {yc:.3f}); "
+          f"cold/hot wall gradient {cold / hot:.3f} (mu ratio {mu_ratio:.3f})", flush=True)
+    assert s.diag()["bad"] == 0
+    assert max(e) < TOL["f32"], e
+    assert abs(cold / hot / mu_ratio - 1) < 0.07
+    if Ra < 1e5:
+        assert xc > 0.55 and yc < 0.45

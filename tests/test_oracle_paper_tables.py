@@ -95,3 +95,47 @@ def test_table2_cavity_ra1e3():
         assert abs(m[k] / row[k] - 1) < 0.02, (k, m[k], row[k])
     for k in ("y_max", "x_max"):
         assert abs(m[k] - row[k]) < 2 / 63 + 1e-9, (k, m[k], row[k])
+
+
+def _sutherland_ratio(Th=1.6, Tl=0.4, S=110.5 / 600.0):
+    """mu(T_h) / mu(T_l) under Eq. 59 (T in units of T_r = 600 K, S = 110.5 K)."""
+    return (Th / Tl) ** 1.5 * (Tl + S) / (Th + S)
+
+
+@pytest.mark.parametrize("name,nodes", [("large_dt_sweep_1e3.npz", 101), ("large_dt_sweep_1e4.npz", 151)])
+def test_large_dT_oracle_fields_show_the_vortex_shift(name, nodes):
+    """The oracle's large-dT cavities at Ra = 1e3 and 1e4 (Sec. IV-C: 960 K /
+    240 K walls, Sutherland viscosity; fields on every 5th node, written by
+    tests/reference_runs.py) show what Figs. 7-8 show: the centre of the
+    primary vortex, the extremum of the stream function (the sum over the
+    sampled rows of rho u_x), sits right of and below the cavity centre, the
+    hot wall being at x = 0.  (At Ra = 1e5 the stream function has a broad
+    two-cell plateau and its extremum does not mark one centre.)"""
+    import numpy as np
+
+    z = np.load(os.path.join(GOLD, name))
+    psi = np.cumsum(z["rho"] * z["ux"], axis=0)
+    j, i = np.unravel_index(np.argmax(np.abs(psi)), psi.shape)
+    x = (int(z["offset"]) + i * int(z["stride"])) / (nodes - 1)
+    y = (int(z["offset_y"]) + j * int(z["stride_y"])) / (nodes - 1)
+    assert x > 0.55 and y < 0.45, (x, y)
+
+
+@pytest.mark.parametrize("name", ["large_dt_sweep_1e3.npz", "large_dt_sweep_1e4.npz", "large_dt_sweep_1e5.npz"])
+def test_large_dT_oracle_wall_heat_fluxes_balance(name):
+    """In a steady cavity the heat entering at the hot wall leaves at the cold
+    one (the other walls are adiabatic).  The conductivity is proportional to
+    mu(T) at fixed Pr, and each x-side is isothermal, so the mean temperature
+    gradient at the cold wall over that at the hot wall is mu(T_h) / mu(T_l)
+    = 2.619 under Eq. 59.  The oracle's fields (second-order one-sided
+    gradients) give 2.56, 2.54 and 2.46 at Ra = 1e3, 1e4 and 1e5; the last,
+    after 300,000 steps, is still approaching steady state (its viscous time
+    H^2/nu is about 670,000 steps)."""
+    import numpy as np
+
+    z = np.load(os.path.join(GOLD, name))
+    L, R = z["T_left3"], z["T_right3"]
+    hot = np.abs(-3 * L[:, 0] + 4 * L[:, 1] - L[:, 2]).mean() / 2
+    cold = np.abs(3 * R[:, 2] - 4 * R[:, 1] + R[:, 0]).mean() / 2
+    assert L[:, 0].min() == pytest.approx(1.6) and R[:, 2].max() == pytest.approx(0.4)
+    assert abs(cold / hot / _sutherland_ratio() - 1) < 0.07, cold / hot
