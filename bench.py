@@ -103,6 +103,31 @@ def time_gpu(n: int, storage: str, steps: int, warmup: int, strip_rows: int = 0,
     return out
 
 
+def copy_bandwidth(reps: int = 5):
+    """A plain device copy of 2 GiB (torch's copy kernel), timed with HIP
+    events: the practical HBM ceiling beside the nominal 8 TB/s, and the
+    calibration run of the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+
+    x = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
+    x.fill_(1.0)
+    y = torch.empty_like(x)
+    y.copy_(x)
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record()
+    for _ in range(reps):
+        y.copy_(x)
+    stop.record()
+    torch.cuda.synchronize()
+    ms = start.elapsed_time(stop) / reps
+    out = {"copy_bytes_read": x.numel() * 4, "copy_bytes_written": x.numel() * 4,
+           "copy_GBs": 2 * x.numel() * 4 / (ms * 1e-3) / 1e9}
+    del x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def _cpu_model() -> str:
     try:
         out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
@@ -286,19 +311,7 @@ def main():
         sys.exit(2)
 
     if args.copy_only:
-        import torch
-
-        x = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
-        x.fill_(1.0)
-        y = torch.empty_like(x)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(5):
-            y.copy_(x)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / 5
-        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": x.numel() * 4,
-                          "copy_GBs": 2 * x.numel() * 4 / dt / 1e9}), flush=True)
+        print(json.dumps(copy_bandwidth()), flush=True)
         return
 
     if args.serving_only:
@@ -338,6 +351,7 @@ def main():
     alg = BYTES_PER_NODE["f32"] * nodes
     achieved = alg / (head["ms_per_step"] * 1e-3) / 1e9
     traffic = measured_traffic(f"lb_step_periodic{args.n}_f32", nodes)
+    copy = copy_bandwidth()
     line = {
         "metric": "MLUPS (FP32 storage) + % HBM roofline",
         "value": round(head["mlups"], 1),
@@ -356,7 +370,8 @@ def main():
                    "nodes": nodes, "strip_rows": head["strip_rows"]},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4), "traffic": traffic,
-                     "bytes_per_node": BYTES_PER_NODE["f32"], "kernel": "k_step<F32, periodic>"},
+                     "bytes_per_node": BYTES_PER_NODE["f32"], "kernel": "k_step<F32, periodic>",
+                     "copy_GBs": round(copy["copy_GBs"], 1), "frac_of_copy": round(achieved / copy["copy_GBs"], 4)},
         "extra": extra,
         "bad_nodes": head["bad_nodes"],
     }

@@ -15,7 +15,10 @@
  * Units: lattice units, dx = dt = c = 1, so R * T0 must equal 1/3 (Sec. II,
  * Sec. IV-A); lb_create rejects other values.
  *
- * Arithmetic: liblbddf.so computes the step in FP32.  liblbddf_fp64.so, built
+ * Arithmetic: liblbddf.so computes the step in FP32; on grids with walls and
+ * FP32 storage it forms the moment sums, the non-equilibrium parts m - m_eq
+ * and h - h_eq and the wall rebuild in FP64 and applies the increments in
+ * FP32 (the long gravity-driven cavity runs need it).  liblbddf_fp64.so, built
  * from the same source, exports the same ABI with the step's arithmetic in
  * FP64 and the same storage formats and state layout; its FP32 stores round
  * stochastically (about half the throughput; for flows whose FP32 rounding
@@ -25,7 +28,9 @@
  *
  * Memory: the caller owns one device buffer of lb_state_bytes() bytes
  * (256-byte aligned) and keeps it alive until lb_destroy.  The library
- * allocates no device memory; it keeps only host-side state.  All device work
+ * allocates no device memory; it keeps host-side state, the hipGraph of its
+ * step batches, and one static 64 KiB device array per GPU that
+ * lb_diag_noalloc uses for partial sums.  All device work
  * runs asynchronously on the HIP stream given to lb_create (NULL: the null
  * stream); calls that return data to host memory synchronise that stream.
  *
@@ -89,7 +94,7 @@ typedef struct {
 
 typedef struct {
     int32_t nx, ny;      /* node counts, boundary nodes included */
-    int32_t storage;     /* lb_storage: population storage type (arithmetic is FP32) */
+    int32_t storage;     /* lb_storage: population storage type */
     int32_t energy;      /* lb_energy: Eq. 18b/47 or internal energy (Eq. 38) */
     int32_t heating;     /* 1: viscous-heating coupling term of Eq. 47 (total energy only) */
     int32_t correction;  /* 1: correction term of Eq. 48-50 */

@@ -884,24 +884,49 @@ __device__ __forceinline__ int col_wrap(const KArgs &a, int x, bool &xin) {
 // lanes 0..31 take column x0 - 1, lanes 32..63 column x0 + 64, row
 // yb + dir (lane & 31); lanes past the strip's end repeat its last row and go
 // unused, and a side that is not needed is skipped.  One wide gather thus
-// serves 32 rows; the row loop picks its values out with readlane.
-template <int ST, bool BC, class F>
-__device__ __forceinline__ real halo_chunk(const KArgs &a, const Planes &S, int x0, int lane, int yb, int dir,
-                                            int ylo, int yhi, bool need_l, bool need_r, unsigned step) {
+// serves 32 rows; the row loop picks its values out with readlane.  The
+// gather is split into the issue of its loads and the finish, so that the
+// strip's first chunk is in flight together with its first rows.
+struct HaloPos {
+    int xw, y;
+    bool xin, on;
+};
+
+__device__ __forceinline__ HaloPos halo_pos(const KArgs &a, int x0, int lane, int yb, int dir, int ylo, int yhi,
+                                            bool need_l, bool need_r) {
     const bool left = lane < kHaloRows;
+    HaloPos h;
+    h.on = left ? need_l : need_r;
+    h.xw = col_wrap(a, left ? x0 - 1 : x0 + kTile, h.xin);
+    h.y = min(max(yb + dir * (lane & (kHaloRows - 1)), ylo), yhi);
+    return h;
+}
+
+template <int ST, bool BC>
+__device__ __forceinline__ void halo_issue(const KArgs &a, const Planes &S, const HaloPos &h, real dh[18]) {
+    if (h.on) row_issue<ST, BC>(a, S, h.xw, h.y, dh);
+}
+
+template <int ST, bool BC, class F>
+__device__ __forceinline__ real halo_finish(const KArgs &a, const Planes &S, const HaloPos &h, real dh[18],
+                                            unsigned step) {
     real qx = real(0.);
-    if (left ? need_l : need_r) {
-        bool hxin;
-        const int hxw = col_wrap(a, left ? x0 - 1 : x0 + kTile, hxin);
-        const int hy = min(max(yb + dir * (lane & (kHaloRows - 1)), ylo), yhi);
-        real dh[18];
+    if (h.on) {
         Mom mh;
         double bwh[2];
         real qy;
-        row_issue<ST, BC>(a, S, hxw, hy, dh);
-        row_finish<ST, BC, F>(a, S, hxw, hxin, hy, dh, mh, bwh, qx, qy, step);
+        row_finish<ST, BC, F>(a, S, h.xw, h.xin, h.y, dh, mh, bwh, qx, qy, step);
     }
     return qx;
+}
+
+template <int ST, bool BC, class F>
+__device__ __forceinline__ real halo_chunk(const KArgs &a, const Planes &S, int x0, int lane, int yb, int dir,
+                                            int ylo, int yhi, bool need_l, bool need_r, unsigned step) {
+    const HaloPos h = halo_pos(a, x0, lane, yb, dir, ylo, yhi, need_l, need_r);
+    real dh[18];
+    halo_issue<ST, BC>(a, S, h, dh);
+    return halo_finish<ST, BC, F>(a, S, h, dh, step);
 }
 
 // One strip: LW wavefronts side by side, wavefront w owning the 64 aligned
@@ -941,8 +966,6 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
     // halo Q_x from the gathered chunk (outer wavefronts only; a column
     // outside a bounded axis has Q = 0 and is not gathered)
     const bool need_l = edge_l && (a.per_x || x0 > 0), need_r = edge_r && (a.per_x || x0 + kTile < a.nx);
-    real qh = real(0.);
-    if (need_l || need_r) qh = halo_chunk<ST, BC, F>(a, S, x0, lane, ys, dir, y0, y1 - 1, need_l, need_r, step);
 
     // two row states used alternately (the loop is unrolled by two); qyb is
     // Q_y of the row behind the current one
@@ -950,9 +973,18 @@ __device__ __forceinline__ void run_strip(const KArgs &a, const char *__restrict
     Mom mA, mB;
     double bwA[2], bwB[2];  // FP64 wall values (bounded grids)
     real qyb, qxA, qyA, qxB, qyB;
-    row_issue<ST, BC>(a, S, xw, ys - dir, dA);
-    row_finish<ST, BC, F>(a, S, xw, xin, ys - dir, dA, mA, bwA, qxA, qyb, step);
-    row_issue<ST, BC>(a, S, xw, ys, dA);
+    // the first halo chunk, the row behind the first and the first row: all
+    // their loads in flight at once (a short strip is bound by their latency)
+    const HaloPos hp = halo_pos(a, x0, lane, ys, dir, y0, y1 - 1, need_l, need_r);
+    real qh;
+    {
+        real dh[18];
+        halo_issue<ST, BC>(a, S, hp, dh);
+        row_issue<ST, BC>(a, S, xw, ys - dir, dB);
+        row_issue<ST, BC>(a, S, xw, ys, dA);
+        qh = halo_finish<ST, BC, F>(a, S, hp, dh, step);
+    }
+    row_finish<ST, BC, F>(a, S, xw, xin, ys - dir, dB, mB, bwB, qxB, qyb, step);
     int kA = row_finish<ST, BC, F>(a, S, xw, xin, ys, dA, mA, bwA, qxA, qyA, step), kB;
     int sc = 0;  // LDS slot of the current row
     if (LW > 1) {
