@@ -168,7 +168,10 @@ def cpu_baseline(seconds: float):
     from oracle import oracle as O
     from paper_1109_6672_amd import workloads as W
 
-    O.set_threads(os.cpu_count() or 1)
+    # the host's CPU share: OMP_NUM_THREADS when set, else the cores this
+    # process may run on
+    want = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0)) or 1
+    O.set_threads(want)
     cores = O.threads()
     p = W.periodic(512)
     f = W.gaussian_fields(p, sigma=1e-3)
