@@ -103,26 +103,32 @@ def time_gpu(n: int, storage: str, steps: int, warmup: int, strip_rows: int = 0,
     return out
 
 
-def copy_bandwidth(reps: int = 5):
-    """A plain device copy of 2 GiB (torch's copy kernel), timed with HIP
-    events: the practical HBM ceiling beside the nominal 8 TB/s, and the
-    calibration run of the FETCH_SIZE / WRITE_SIZE counters."""
+def copy_bandwidth(reps: int = 5, probe: bool = True):
+    """A plain device copy of 2 GiB timed with HIP events: with probe, the
+    library's STREAM-like copy (lb_copy_probe), the practical memory ceiling
+    beside the nominal 8 TB/s; else torch's copy, the calibration run of the
+    FETCH_SIZE / WRITE_SIZE counters."""
     import torch
+
+    from paper_1109_6672_amd import lbddf
 
     x = torch.empty(1 << 29, dtype=torch.float32, device="cuda")
     x.fill_(1.0)
     y = torch.empty_like(x)
-    y.copy_(x)
+    run = (lambda: lbddf.copy_probe(x, y)) if probe else (lambda: y.copy_(x))
+    run()
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     start.record()
     for _ in range(reps):
-        y.copy_(x)
+        run()
     stop.record()
     torch.cuda.synchronize()
     ms = start.elapsed_time(stop) / reps
-    out = {"copy_bytes_read": x.numel() * 4, "copy_bytes_written": x.numel() * 4,
-           "copy_GBs": 2 * x.numel() * 4 / (ms * 1e-3) / 1e9}
+    if probe and not torch.equal(x, y):
+        raise RuntimeError("copy probe: destination differs from the source")
+    out = {"copy_kernel": "lb_copy_probe" if probe else "torch copy_", "copy_bytes_read": x.numel() * 4,
+           "copy_bytes_written": x.numel() * 4, "copy_GBs": 2 * x.numel() * 4 / (ms * 1e-3) / 1e9}
     del x, y
     torch.cuda.empty_cache()
     return out
@@ -237,7 +243,8 @@ def serving_compare(n_requests: int = 24, sizes=(64, 128, 256), k_steps: int = 1
 def pmc_summary(run_dir: str, n: int = 8192) -> dict:
     """HBM bytes per launch of the headline step from rocprofv3 PMC runs under
     run_dir ({f32,f16}fetch and {f32,f16}write with FETCH_SIZE / WRITE_SIZE,
-    the FP16 pair optional; cfetch and cwrite on --copy-only).  The scales come from the copy: bytes it
+    the FP16 pair optional; cfetch and cwrite on --copy-only, whose k_copy
+    dispatches each copy 2 GiB).  The scales come from the copy: bytes it
     moved over the KiB each counter reports for it.  Returns the entries of
     profiles/traffic.json for the current device code."""
     import csv
@@ -252,8 +259,8 @@ def pmc_summary(run_dir: str, n: int = 8192) -> dict:
             raise ValueError("no matching dispatches")
         return sum(v) / len(v)
 
-    copy = lambda k: "copyBuffer" in k
-    copied_kib = 2 * 2**30 / 1024  # --copy-only copies 2 GiB
+    copy = lambda k: "k_copy" in k  # the library's copy probe: every dispatch copies 2 GiB
+    copied_kib = 2 * 2**30 / 1024
     fetch_scale = round(copied_kib / mean(values("cfetch", "FETCH_SIZE", copy)), 2)
     write_scale = round(copied_kib / mean(values("cwrite", "WRITE_SIZE", copy)), 2)
     sha, out = kernel_source_hash(), {}
@@ -297,7 +304,7 @@ def main():
     ap.add_argument("--workload", default="periodic",
                     help="workload of an --only run: periodic (n x n) | cavity512 | channel2048x256")
     ap.add_argument("--copy-only", action="store_true",
-                    help="HBM counter calibration: 5 plain device copies of 2 GiB (torch copy kernel)")
+                    help="HBM counter calibration and copy ceiling: the library's copy probe over 2 GiB")
     ap.add_argument("--pmc-summary", metavar="DIR", default="",
                     help="no GPU: write profiles/traffic.json from the rocprofv3 PMC runs under DIR")
     args = ap.parse_args()

@@ -206,6 +206,16 @@ lb_status lb_load(lb_handle *h, const void *host_buf);
 lb_status lb_set_strip_rows(lb_handle *h, int rows);
 int lb_strip_rows(const lb_handle *h);
 
+/* Bandwidth reference (not part of the method): copies `bytes` from src to
+ * dst, both device pointers, 16-byte aligned, not overlapping, bytes a
+ * multiple of 16, with a STREAM-like kernel (16-byte vector loads, four in
+ * flight per lane, non-temporal stores), asynchronously on hip_stream (NULL:
+ * the null stream).  Timing it gives the practical memory ceiling beside the
+ * nominal peak against which the step's algorithmic bytes per second are
+ * read.  LB_EINVAL for null, misaligned or overlapping buffers; LB_EHIP when
+ * the launch fails. */
+lb_status lb_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);
+
 /* The HIP stream the handle launches on (a hipStream_t). */
 void *lb_stream(const lb_handle *h);
 

@@ -73,6 +73,7 @@ _SIGS = {
     "lb_set_graph_steps": (C.c_int, [C.c_void_p, C.c_int]),
     "lb_strip_rows": (C.c_int, [C.c_void_p]),
     "lb_stream": (C.c_void_p, [C.c_void_p]),
+    "lb_copy_probe": (C.c_int, [C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "lb_destroy": (None, [C.c_void_p]),
     "lb_last_error": (C.c_char_p, []),
     "lbs_pool_overhead": (C.c_size_t, []),
@@ -157,6 +158,21 @@ def state_bytes(p: dict) -> int:
 
 def validate(p: dict) -> None:
     _check(load().lb_validate(C.byref(make_params(p))))
+
+
+def copy_probe(src, dst, stream=None) -> None:
+    """lb_copy_probe: the library's STREAM-like copy of the device tensor src
+    into dst (same byte size, 16-byte aligned), asynchronously on the given
+    torch stream (default: the current one); the practical memory ceiling
+    that the step's bandwidth is read against."""
+    import torch
+
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("copy_probe: src and dst differ in size")
+    st = stream if stream is not None else torch.cuda.current_stream()
+    _check(load().lb_copy_probe(C.c_void_p(src.data_ptr()), C.c_void_p(dst.data_ptr()), nbytes,
+                                C.c_void_p(st.cuda_stream)))
 
 
 def _dptr(a):

@@ -53,8 +53,11 @@ def test_pmc_summary_scales_the_counters_by_the_copy(tmp_path):
     """A copy of 2 GiB that FETCH_SIZE reports as 1 GiB gives a read scale of
     2; the step's bytes are then 2 x fetch + 1 x write, in KiB x 1024."""
     d = str(tmp_path)
-    copy = "__amd_rocclr_copyBuffer"
-    _csv(os.path.join(d, "cfetch"), [(copy, "FETCH_SIZE", 1048576.0)] * 3 + [("fill", "FETCH_SIZE", 5.0)])
+    copy = "(anonymous namespace)::k_copy(unsigned int __vector(4) const*, unsigned int __vector(4)*, long long, long long)"
+    # the copy probe's 2 GiB dispatches calibrate; other kernels of the run
+    # (torch's fill and copies of other sizes) are ignored
+    _csv(os.path.join(d, "cfetch"), [(copy, "FETCH_SIZE", 1048576.0)] * 3 + [("fill", "FETCH_SIZE", 5.0),
+                                                                            ("__amd_rocclr_copyBuffer", "FETCH_SIZE", 2.0)])
     _csv(os.path.join(d, "cwrite"), [(copy, "WRITE_SIZE", 2097152.0)] * 3)
     for st, code in (("f32", 0), ("f16", 1)):
         k = f"void (anonymous namespace)::k_step<{code}, false, (anonymous namespace)::Head>(...)"
