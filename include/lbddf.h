@@ -226,8 +226,9 @@ void lb_destroy(lb_handle *h);
 const char *lb_last_error(void);
 
 /* ------------------------------------------------------------------------
- * Serving: continuous batching of many grids (cavity or channel solves of
- * uneven sizes) in one packed launch per time step.
+ * Serving: continuous batching of many grids of uneven sizes (cavities,
+ * periodic boxes, grids with an outlet; not an inlet) in one packed launch
+ * per time step.
  *
  * The caller hands the server one device pool; the server keeps the state of
  * every admitted request resident in it and admits queued requests first in,
