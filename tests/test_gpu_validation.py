@@ -3,14 +3,18 @@ against what the paper and the mathematics fix there:
 
 * the bench workload (periodic 8192 x 8192) element by element against the
   FP64 oracle after 5 steps;
+* the periodic 1024^2 (1000 steps) and 4096^2 (10 steps) grids and the
+  first 5000 steps of the 2048 x 256 channel against sampled oracle fields;
 * the small-dT cavity (128 x 128, Ra = 1e4) run to convergence against the
-  'Present' row of Table II;
+  'Present' row of Table II and against the oracle, and the other Table II
+  rows (Ra = 1e3, 1e5; Ra = 1e4 at the paper's temperatures on 151^2);
 * the acoustic channel (2048 x 256, sinusoidal source at x = 0) against the
   attenuation law Eq. 55-56 before the outlet reflection returns, then on to
   100,000 steps;
-* the large-dT cavity (Sutherland viscosity) on its 64 x 64 form against the
-  FP64 oracle after 200,000 steps in FP32, FP16 and BF16 storage, and at
-  512 x 512 the heat-flux balance of the two walls.
+* the large-dT cavity (Sutherland viscosity) on its 64 x 64 form and at
+  512 x 512 against the FP64 oracle after 200,000 steps in FP32, FP16 and
+  BF16 storage, the heat-flux balance of its two walls, and the paper's Ra
+  sweep on 101^2, 151^2 and 201^2.
 """
 import json
 import math
@@ -153,9 +157,9 @@ def test_table_ii_ra1e4_at_the_papers_temperatures_and_grid():
 
 def test_small_dT_cavity_converged_state_against_the_oracle():
     """Config 2 run 268,000 steps (its convergence above) on the GPU and in the
-    FP64 oracle: FP32 arithmetic with FP32 storage within 1e-5 in rho, u and
-    T (measured 1.3e-7 / 5.0e-6 / 7.9e-8), and the Table II quantities agree
-    to 1e-4.  This flow's velocity (about 3.5e-3) is driven by a buoyancy
+    FP64 oracle: FP32 storage within 1e-5 in rho, u and T (measured 9.1e-8 /
+    1.3e-6 / 2.8e-8 with the walled step's FP64 sums), and the Table II
+    quantities agree to 1e-4.  This flow's velocity (about 3.5e-3) is driven by a buoyancy
     fifty times smaller than the hydrostatic forces (dT/T0 = 0.02), so a
     steady per-step bias of the energy balance shows up in u: before the
     zeroth moment of h_eq was closed on the node's energy, the rounding of the
@@ -244,8 +248,8 @@ def large_dT_reference():
 
 def test_large_dT_cavity_downscale_against_the_oracle(large_dT_reference):
     """The 64 x 64 form (g = 1.7e-3, g H / R T0 = 0.32) after 200,000 steps,
-    FP32 storage: within 1e-5 of the oracle (measured 2.1e-6 / 1.1e-6 /
-    6.7e-7).  The deviations from the rest state are O(1) here (rho from 0.6
+    FP32 storage: within 1e-5 of the oracle (measured 2.7e-7 / 3.7e-7 /
+    2.7e-7).  The deviations from the rest state are O(1) here (rho from 0.6
     to 2.5); the bounded-grid step forms the moments, m - m_eq, h - h_eq and
     the wall rebuild in FP64 and rounds its FP32 sums without bias (FP32
     throughout: 3.5e-5 / 1.5e-5 / 1.3e-5)."""
@@ -311,10 +315,10 @@ def test_large_dT_cavity_512_against_the_oracle(arith):
     """Config 3 at full size: 512 x 512, 200,000 steps, FP32 storage, against
     the FP64 oracle's fields on every 8th node
     (tests/golden/large_dt_512_sample.npz, written by tests/reference_runs.py
-    from an oracle-only run).  Measured: FP32 arithmetic 4.5e-7 / 3.2e-6 /
-    4.5e-7 (with the moments, the non-equilibrium parts and the wall rebuild
+    from an oracle-only run).  Measured: the FP32 library 3.1e-7 / 3.0e-6 /
+    2.6e-7 (with the moments, the non-equilibrium parts and the wall rebuild
     in FP32 and plain rounding: 8e-5 / 7.5e-5 / 1.3e-4); the FP64-arithmetic
-    library 2.5e-7 / 3.4e-6 / 2.9e-7."""
+    library 2.8e-7 / 3.4e-6 / 3.1e-7."""
     s, e = _large_dt_512("f32", arith)
     assert s.diag()["bad"] == 0
     assert max(e) < TOL["f32"], e
