@@ -29,6 +29,23 @@ def test_cpu_baseline_reports_the_contract_fields():
     assert c["kind"] == "oracle" and c["unit"] == "MLUPS" and c["value"] > 0 and c["cores"] >= 1
 
 
+def test_cpu_baseline_uses_the_cpu_share(monkeypatch):
+    """The oracle runs on OMP_NUM_THREADS threads when that is set (the host's
+    CPU share), and `cores` reports the threads it used."""
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liborc.so")):
+        pytest.skip("oracle not built")
+    from oracle import oracle as O
+
+    before = O.threads()
+    monkeypatch.setenv("OMP_NUM_THREADS", "2")
+    try:
+        c = bench.cpu_baseline(0.2)
+    finally:
+        O.set_threads(before)
+    assert c["cores"] == 2
+    assert c["samples"][0]["threads"] == 2 and c["samples"][1]["threads"] == 1
+
+
 def test_traffic_is_reported_only_for_the_profiled_device_code():
     h = bench.kernel_source_hash()
     assert len(h) == 16
