@@ -93,14 +93,24 @@ def test_paper_couette_power_law_adiabatic(gpu):
     _check(e, "f32")
 
 
-@pytest.mark.parametrize("storage,steps", [("f32", 12000), ("f16", 1000)])
+_F16_GRAVITY_MISS = pytest.mark.xfail(
+    raises=AssertionError, strict=True,
+    reason="FP16 storage of the gravity-stratified deviations from rest: u measured 7.8e-3 against 2e-3 after "
+           "12,000 steps (7.4e-3 after 4000; rho and T 2.5e-4 and 2.3e-4)")
+
+
+@pytest.mark.parametrize("storage,steps", [("f32", 12000), ("f16", 1000),
+                                           pytest.param("f16", 12000, marks=_F16_GRAVITY_MISS)])
 def test_cavity_small_dT(gpu, storage, steps):
     """Gravity-driven small-dT cavity, tau_f = 0.56 as in the 128^2 case
     (0.536 is unstable in the oracle itself).  FP32 storage over 12,000 steps
     (measured 4.8e-8 / 1.2e-6 / 5.1e-8; the full convergence run is in the
-    validation tests); FP16 storage over 1000 steps."""
+    validation tests).  FP16 storage meets the 16-bit bar over the first 1000
+    steps only: the flow's velocity is a small residue of stratified
+    populations whose FP16 rounding noise accumulates in u."""
     p = W.cavity(70, 1e4, 0.02, 0.02, storage=storage)
     _, _, _, _, e = run_pair(p, W.noisy_temperature_fields(p), steps, "cavity small dT")
+    _finite(e)
     _check(e, storage)
 
 
