@@ -52,13 +52,13 @@ def measured_traffic(key: str, nodes: int):
 
 
 def bounded_case(kind: str, storage: str):
-    """The bounded configurations: the large-dT cavity at 512^2 (walls on all
-    sides, Sutherland viscosity) and the acoustic channel 2048 x 256 (inlet,
-    outlet, periodic in y)."""
+    """The bounded configurations: the large-dT cavity at 512^2 and 2048^2
+    (walls on all sides, Sutherland viscosity) and the acoustic channel
+    2048 x 256 (inlet, outlet, periodic in y)."""
     from paper_1109_6672_amd import workloads as W
 
-    if kind == "cavity512":
-        p = W.cavity(512, 1e5, 1.2, 0.06, sutherland=True, storage=storage)
+    if kind in ("cavity512", "cavity2048"):
+        p = W.cavity(int(kind[6:]), 1e5, 1.2, 0.06, sutherland=True, storage=storage)
         p.update(s_e=1.5, s_zeta=1.5)
         return p, W.conduction_fields(p)
     p = W.channel(2048, 256, U0=0.01, period=200.0, storage=storage)
@@ -302,7 +302,7 @@ def main():
                     help="steps per batch and between residual checks (the residual is the change over them)")
     ap.add_argument("--only", default="", help="storage of a single run (profiling): f32 | f16 | bf16")
     ap.add_argument("--workload", default="periodic",
-                    help="workload of an --only run: periodic (n x n) | cavity512 | channel2048x256")
+                    help="workload of an --only run: periodic (n x n) | cavity512 | cavity2048 | channel2048x256")
     ap.add_argument("--copy-only", action="store_true",
                     help="HBM counter calibration and copy ceiling: the library's copy probe over 2 GiB")
     ap.add_argument("--pmc-summary", metavar="DIR", default="",
@@ -355,8 +355,10 @@ def main():
         print(f"# f32 storage, FP64 arithmetic {args.n}^2: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
         # the bounded grids take ~20 us per step: time whole graph batches
         # (2048 steps, 64 replays of 32) after as many warm-up steps
-        for case, storage in (("cavity512", "f32"), ("cavity512", "f16"), ("channel2048x256", "f32")):
-            r = time_gpu(0, storage, max(args.steps, 2048), max(args.warmup, 64), case=case)
+        for case, storage in (("cavity512", "f32"), ("cavity512", "f16"), ("channel2048x256", "f32"),
+                              ("cavity2048", "f32")):
+            steps = max(args.steps, 2048) if case != "cavity2048" else max(args.steps, 256)
+            r = time_gpu(0, storage, steps, max(args.warmup, 64), case=case)
             extra[f"{storage}_{case}"] = {k: r[k] for k in ("mlups", "gbs", "ms_per_step", "strip_rows")}
             print(f"# {storage} {case}: {r['mlups']:.0f} MLUPS", file=sys.stderr, flush=True)
     nodes = args.n * args.n
