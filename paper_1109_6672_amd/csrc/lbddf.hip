@@ -1061,17 +1061,20 @@ __global__ __launch_bounds__(kWave * kLock<ST>) void k_step(const KArgs a, const
 // Sets the step clock that the launches of a captured graph read.
 __global__ void k_set_clock(long long *clk, long long n) { clk[0] = n; }
 
-// Packed step of many grids (serving).  The work list holds, first, the
-// block items of the wide grids (FP32 storage, at least kWavesPerBlock tiles
-// across): a block runs kWavesPerBlock adjacent tiles of one strip in
+// Packed step of many grids (serving).  The work list has two parts: the
+// items of the grids in the cavity configuration, stepped by a launch of the
+// kernel specialised for it (CavW), then those of the other grids (DynW), by
+// a launch of the general one; a grid's kernel follows from its own switches,
+// so its arithmetic does not depend on the mix.  Within a part come, first,
+// the block items of the wide grids (FP32 storage, at least kWavesPerBlock
+// tiles across): a block runs kWavesPerBlock adjacent tiles of one strip in
 // lockstep, as the single-grid step does; then the wavefront items of the
 // narrow grids (all grids of the 16-bit codecs), one tile of one strip each,
-// run by the wavefronts of a block independently.  One kernel, a fixed grid of
-// blocks numbered XCD by XCD so that runs of neighbouring items share an L2,
-// goes over the list in rounds: the wide grids' items first, then the narrow
-// ones four to a block.  A grid is always wide or always narrow, so its
-// arithmetic does not depend on the mix.  Call i of a batch reads buffer
-// (cur + i) & 1 of each grid.
+// run by the wavefronts of a block independently.  One kernel, a fixed grid
+// of blocks numbered XCD by XCD so that runs of neighbouring items share an
+// L2, goes over its part in rounds: the wide grids' items first, then the
+// narrow ones four to a block.  A grid is always wide or always narrow.  Call
+// i of a batch reads buffer (cur + i) & 1 of each grid.
 struct SlotDev {
     KArgs a;
     const char *pops[2];
@@ -1082,15 +1085,22 @@ struct WorkItem {
     int slot, tx, sy, pad_;
 };
 
-// 3 wavefronts per SIMD for the 16-bit codecs (168 VGPRs); 2 with FP32
-// storage, whose served grids (all bounded) form their moments in FP64 and
-// carry both the wide and the narrow path.  The 16-bit codecs have the narrow
-// path only (measured: the wide one made their packed step slower).
+// 2 wavefronts per SIMD with FP32 storage, whose served grids (all bounded)
+// form their moments in FP64 and carry both the wide and the narrow path; 3
+// for the 16-bit codecs, which have the narrow path only (measured: the wide
+// one made their packed step slower).
 template <int ST>
-__global__ __launch_bounds__(kBlock, ST == LB_STORE_F32 ? 2 : 3) void k_step_multi(const SlotDev *__restrict__ slots,
-                                                          const WorkItem *__restrict__ items,
-                                                          const int *__restrict__ counts, int i) {
-    const int nwide = counts[0], nnarrow = counts[1];
+constexpr int kMultiWaves = ST == LB_STORE_F32 ? 2 : 3;
+
+// counts = {wide, narrow items of part 0, wide, narrow items of part 1}; the
+// items of part 1 follow those of part 0.
+template <int ST, class F>
+__global__ __launch_bounds__(kBlock, kMultiWaves<ST>) void k_step_multi(const SlotDev *__restrict__ slots,
+                                                                         const WorkItem *__restrict__ items,
+                                                                         const int *__restrict__ counts, int part,
+                                                                         int i) {
+    const int nwide = counts[2 * part], nnarrow = counts[2 * part + 1];
+    if (part) items += counts[0] + counts[1];
     const int nblk = nwide + (nnarrow + kWavesPerBlock - 1) / kWavesPerBlock;
     const int wv = (int)(threadIdx.x >> 6);
     // Rounds of gridDim.x block items; in each, the m blocks that have one
@@ -1106,8 +1116,8 @@ __global__ __launch_bounds__(kBlock, ST == LB_STORE_F32 ? 2 : 3) void k_step_mul
             const WorkItem it = items[b];
             const SlotDev &sd = slots[it.slot];
             const int c = (sd.cur + i) & 1;
-            run_strip<ST, true, DynW, kWavesPerBlock>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]),
-                                                     it.tx + wv, it.sy, (unsigned)(sd.n + i));
+            run_strip<ST, true, F, kWavesPerBlock>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]), it.tx + wv,
+                                                  it.sy, (unsigned)(sd.n + i));
             __syncthreads();  // the next item rewrites the LDS edge slots
         } else {
             // the item index is the same on every lane of the wavefront:
@@ -1118,8 +1128,8 @@ __global__ __launch_bounds__(kBlock, ST == LB_STORE_F32 ? 2 : 3) void k_step_mul
                 const WorkItem it = items[w];
                 const SlotDev &sd = slots[it.slot];
                 const int c = (sd.cur + i) & 1;
-                run_strip<ST, true, DynW, 1>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]), it.tx, it.sy,
-                                            (unsigned)(sd.n + i));
+                run_strip<ST, true, F, 1>(sd.a, sd.pops[c], const_cast<char *>(sd.pops[c ^ 1]), it.tx, it.sy,
+                                         (unsigned)(sd.n + i));
             }
         }
     }
@@ -2133,7 +2143,7 @@ struct lbs_server {
     double *d_results = nullptr;
     std::vector<SlotDev> h_slots;
     std::vector<WorkItem> h_items;
-    int h_counts[2] = {0, 0};  // block items of wide grids, wavefront items of narrow ones
+    int h_counts[4] = {0, 0, 0, 0};  // wide and narrow items of part 0 (cavity grids), of part 1 (others)
     std::vector<double> h_results;
     std::vector<long> slot_req;               // slot -> request id or -1
     std::map<size_t, size_t> free_blocks;     // offset -> bytes
@@ -2141,8 +2151,8 @@ struct lbs_server {
     std::deque<long> queue;
     long next_id = 1;
     long items_resident = 0;  // work-list entries of the resident grids
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph[2] = {nullptr, nullptr};  // k-step batches of part 0 and part 1
+    hipGraphExec_t exec[2] = {nullptr, nullptr};
     double batches = 0, node_updates = 0, busy_s = 0, completed = 0;
 };
 
@@ -2179,21 +2189,28 @@ void pool_free(lbs_server *S, size_t off, size_t bytes) {
     }
 }
 
-lb_status build_graph(lbs_server *S) {
-    HIPCHK(hipGraphCreate(&S->graph, 0));
+template <int ST>
+void *multi_kernel(int part) {
+    return part ? (void *)k_step_multi<ST, DynW> : (void *)k_step_multi<ST, CavW>;
+}
+
+// The k-step graph of one part of the work list: k launches of its packed
+// kernel, launch i stepping every grid of the part from time n + i.
+lb_status build_graph(lbs_server *S, int part) {
+    HIPCHK(hipGraphCreate(&S->graph[part], 0));
     hipGraphNode_t prev = nullptr;
     void *fn = nullptr;
     switch (S->storage) {
-    case LB_STORE_F32: fn = (void *)k_step_multi<LB_STORE_F32>; break;
-    case LB_STORE_F16: fn = (void *)k_step_multi<LB_STORE_F16>; break;
-    default: fn = (void *)k_step_multi<LB_STORE_BF16>; break;
+    case LB_STORE_F32: fn = multi_kernel<LB_STORE_F32>(part); break;
+    case LB_STORE_F16: fn = multi_kernel<LB_STORE_F16>(part); break;
+    default: fn = multi_kernel<LB_STORE_BF16>(part); break;
     }
     for (int i = 0; i < S->k; ++i) {
-        int ii = i;
+        int ii = i, pp = part;
         const SlotDev *a0 = S->d_slots;
         const WorkItem *a1 = S->d_items;
         const int *a2 = S->d_nitems;
-        void *args[4] = {(void *)&a0, (void *)&a1, (void *)&a2, (void *)&ii};
+        void *args[5] = {(void *)&a0, (void *)&a1, (void *)&a2, (void *)&pp, (void *)&ii};
         hipKernelNodeParams kp{};
         kp.func = fn;
         kp.gridDim = dim3(kMultiBlocks);
@@ -2202,11 +2219,20 @@ lb_status build_graph(lbs_server *S) {
         kp.kernelParams = args;
         kp.extra = nullptr;
         hipGraphNode_t node;
-        HIPCHK(hipGraphAddKernelNode(&node, S->graph, prev ? &prev : nullptr, prev ? 1 : 0, &kp));
+        HIPCHK(hipGraphAddKernelNode(&node, S->graph[part], prev ? &prev : nullptr, prev ? 1 : 0, &kp));
         prev = node;
     }
-    HIPCHK(hipGraphInstantiate(&S->exec, S->graph, nullptr, nullptr, 0));
+    HIPCHK(hipGraphInstantiate(&S->exec[part], S->graph[part], nullptr, nullptr, 0));
     return LB_OK;
+}
+
+void drop_server_graphs(lbs_server *S) {
+    for (int part = 0; part < 2; ++part) {
+        if (S->exec[part]) (void)hipGraphExecDestroy(S->exec[part]);
+        if (S->graph[part]) (void)hipGraphDestroy(S->graph[part]);
+        S->exec[part] = nullptr;
+        S->graph[part] = nullptr;
+    }
 }
 
 lb_status admit(lbs_server *S) {
@@ -2315,8 +2341,10 @@ lb_status lbs_create(void *dev_pool, size_t pool_bytes, int storage, int k_steps
     S->h_results.assign((size_t)kMaxSlots * kNred, 0.0);
     S->slot_req.assign(kMaxSlots, -1);
     S->free_blocks[hdr] = (pool_bytes - hdr) / 256 * 256;
-    lb_status st = build_graph(S);
+    lb_status st = build_graph(S, 0);
+    if (st == LB_OK) st = build_graph(S, 1);
     if (st != LB_OK) {
+        drop_server_graphs(S);
         delete S;
         return st;
     }
@@ -2380,19 +2408,24 @@ lb_status lbs_advance(lbs_server *S, int *n_resident, int *n_queued) {
         sd.n = h->n;
         live.push_back(slot);
     }
-    for (int pass = 0; pass < 2; ++pass) {
-        for (int slot : live) {
-            const Request &r = S->reqs[S->slot_req[slot]];
-            const KArgs &a = r.h->a;
-            const int wide = grid_is_wide(&r.p);
-            if (wide != (pass == 0)) continue;
-            const int step = wide ? kWavesPerBlock : 1;
-            for (int sy = 0; sy < a.n_strips; ++sy)
-                for (int tx = 0; tx < a.tiles_x; tx += step) S->h_items.push_back(WorkItem{slot, tx, sy, 0});
+    // part 0: the grids in the cavity configuration, part 1: the others;
+    // within each, the wide grids' block items, then the narrow ones'
+    for (int part = 0; part < 2; ++part) {
+        for (int pass = 0; pass < 2; ++pass) {
+            const size_t before = S->h_items.size();
+            for (int slot : live) {
+                const Request &r = S->reqs[S->slot_req[slot]];
+                const KArgs &a = r.h->a;
+                if (is_cavity(a) != (part == 0)) continue;
+                const int wide = grid_is_wide(&r.p);
+                if (wide != (pass == 0)) continue;
+                const int step = wide ? kWavesPerBlock : 1;
+                for (int sy = 0; sy < a.n_strips; ++sy)
+                    for (int tx = 0; tx < a.tiles_x; tx += step) S->h_items.push_back(WorkItem{slot, tx, sy, 0});
+            }
+            S->h_counts[2 * part + pass] = (int)(S->h_items.size() - before);
         }
-        if (pass == 0) S->h_counts[0] = (int)S->h_items.size();
     }
-    S->h_counts[1] = (int)S->h_items.size() - S->h_counts[0];
     if (n_resident) *n_resident = (int)live.size();
     if (n_queued) *n_queued = (int)S->queue.size();
     if (live.empty()) return LB_OK;
@@ -2403,8 +2436,9 @@ lb_status lbs_advance(lbs_server *S, int *n_resident, int *n_queued) {
     const int nitems = (int)S->h_items.size();
     HIPCHK(hipMemcpyAsync(S->d_slots, S->h_slots.data(), kMaxSlots * sizeof(SlotDev), hipMemcpyHostToDevice, S->stream));
     HIPCHK(hipMemcpyAsync(S->d_items, S->h_items.data(), nitems * sizeof(WorkItem), hipMemcpyHostToDevice, S->stream));
-    HIPCHK(hipMemcpyAsync(S->d_nitems, S->h_counts, 2 * sizeof(int), hipMemcpyHostToDevice, S->stream));
-    HIPCHK(hipGraphLaunch(S->exec, S->stream));
+    HIPCHK(hipMemcpyAsync(S->d_nitems, S->h_counts, 4 * sizeof(int), hipMemcpyHostToDevice, S->stream));
+    for (int part = 0; part < 2; ++part)
+        if (S->h_counts[2 * part] + S->h_counts[2 * part + 1] > 0) HIPCHK(hipGraphLaunch(S->exec[part], S->stream));
     // advance the grids' clocks, then the FP64 residual of each grid in one read-back
     for (int slot : live) {
         Request &r = S->reqs[S->slot_req[slot]];
@@ -2503,8 +2537,7 @@ void lbs_destroy(lbs_server *S) {
     if (!S) return;
     for (auto &kv : S->reqs)
         if (kv.second.h) lb_destroy(kv.second.h);
-    if (S->exec) (void)hipGraphExecDestroy(S->exec);
-    if (S->graph) (void)hipGraphDestroy(S->graph);
+    drop_server_graphs(S);
     delete S;
 }
 
