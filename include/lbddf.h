@@ -199,9 +199,10 @@ lb_status lb_load(lb_handle *h, const void *host_buf);
 
 /* Launch tuning of the step kernel: rows per strip (power of two 1..256;
  * each block of wavefronts marches through one strip of rows), 0 restores
- * the automatic choice (8 rows with FP32 storage, 16 with FP16/BF16, 2 in
- * liblbddf_fp64.so, halved down to 1 while the grid would give fewer than
- * 4096 wavefronts, fully periodic grids, or 2048, bounded ones).  Results do not depend on it.  Returns LB_EINVAL
+ * the automatic choice (8 rows with FP32 storage, 16 with FP16/BF16 and for
+ * FP32 grids with walls, 2 in liblbddf_fp64.so, halved down to 1 while the
+ * grid would give fewer than 4096 wavefronts, fully periodic grids, or 2048,
+ * bounded ones).  Results do not depend on it.  Returns LB_EINVAL
  * for other values. */
 lb_status lb_set_strip_rows(lb_handle *h, int rows);
 int lb_strip_rows(const lb_handle *h);

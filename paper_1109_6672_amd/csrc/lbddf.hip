@@ -1468,12 +1468,15 @@ void set_strip(lb_handle *h) {
     a.tiles_x = (a.nx + kTile - 1) / kTile;
     int R = h->strip_user;
     if (R <= 0) {
-        // 8-row strips for FP32 storage, 16 for the 16-bit codecs (measured
-        // best on 8192^2, 4096^2 and 2048^2); shorter ones, down to 1 row,
-        // while the grid would give fewer wavefronts than a floor: 4096 (16
-        // per CU) for fully periodic grids, 2048 for bounded ones, whose step
-        // is heavier (measured on periodic 1024^2, the 512^2 cavity and the
-        // 2048 x 256 channel in FP32 and FP16)
+        // 8-row strips for FP32 storage, 16 for the 16-bit codecs and for
+        // FP32 grids with walls, whose FP64 row finishes make the two halo
+        // rows of a strip dearer (measured best on 8192^2, 4096^2 and 2048^2;
+        // the 2048^2 cavity in FP32: 156.6 us per step with 16 rows, 164.5
+        // with 8); shorter ones, down to 1 row, while the grid would give
+        // fewer wavefronts than a floor: 4096 (16 per CU) for fully periodic
+        // grids, 2048 for bounded ones, whose step is heavier (measured on
+        // periodic 1024^2, the 512^2 cavity and the 2048 x 256 channel in
+        // FP32 and FP16)
         const bool f32 = h->p.storage == LB_STORE_F32;
         const int lw = f32 ? kLock<LB_STORE_F32> : kLock<LB_STORE_F16>;
         const long long bcols = (a.tiles_x + lw - 1) / lw;
@@ -1483,7 +1486,7 @@ void set_strip(lb_handle *h) {
         // more strips (measured on 8192^2: 2 rows 23.6 GLUPS, 8 rows 20.3)
         R = 2;
 #else
-        R = f32 ? 8 : 16;
+        R = (f32 && !h->walls) ? 8 : 16;
 #endif
         while (R > 1 && bcols * lw * ((a.ny + R - 1) / R) < floor_waves) R >>= 1;
     }
