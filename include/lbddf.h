@@ -237,8 +237,12 @@ const char *lb_last_error(void);
  * resident grids) and room in the packed kernel's work list (2^18 items: one
  * per 4 rows of each 64-column tile, or of each group of four tiles for FP32
  * grids at least 256 columns wide) become free.  One lbs_advance call runs k steps of every
- * resident grid as a hipGraph of k launches of one packed kernel (the same
- * per-node step as lb_step), then reads every grid's FP64 convergence
+ * resident grid as hipGraphs of k launches of a packed kernel (the same
+ * per-node step as lb_step): one for the grids in the cavity configuration
+ * (internal energy, no heating term, coupled, correction, gravity, MRT, a
+ * viscosity law other than constant tau), one for the others, so that a
+ * grid's arithmetic depends on its own parameters only; then it reads every
+ * grid's FP64 convergence
  * residual r = ||T - T_snap|| / ||T|| (snapshot k steps earlier; the first
  * at admission) in one copy,
  * retires grids that converged (r < tol), reached a plateau (r below 1e-2 of
