@@ -235,8 +235,9 @@ const char *lb_last_error(void);
  * every admitted request resident in it and admits queued requests first in,
  * first out as their byte footprint (lb_state_bytes), a slot (at most 512
  * resident grids) and room in the packed kernel's work list (2^18 items: one
- * per 4 rows of each 64-column tile, or of each group of four tiles for FP32
- * grids at least 256 columns wide) become free.  One lbs_advance call runs k steps of every
+ * per strip of each 64-column tile, or of each group of four tiles for FP32
+ * grids at least 256 columns wide; strips of 4 rows, or of 2 for a batch that
+ * would give fewer than 2048 wavefronts, and room is kept for 2) become free.  One lbs_advance call runs k steps of every
  * resident grid as hipGraphs of k launches of a packed kernel (the same
  * per-node step as lb_step): one for the grids in the cavity configuration
  * (internal energy, no heating term, coupled, correction, gravity, MRT, a
